@@ -1,0 +1,520 @@
+"""Pins of the FP64 CPU oracle against facts the paper and mathematics fix.
+
+Each test checks the oracle against something other than itself: values the
+paper prints, closed forms, exact rationals computed by a different method,
+brute-force sums, textbook special cases and the analytic solution of an
+electron in a plane wave (Sec. II and the appendix).
+"""
+
+from fractions import Fraction
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2102_10983_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------------------
+# Lagrange weights (Sec. VI, Eqs. (lagrange2-2), (lagrange2-3))
+# ---------------------------------------------------------------------------
+def _printed_weights():
+    rows = []
+    with open(os.path.join(GOLDEN, "lagrange_printed.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            tok = line.split()
+            rows.append((int(tok[0]), float(tok[1]), int(tok[2]), [int(t) for t in tok[3:]]))
+    return rows
+
+
+@pytest.mark.parametrize("row", _printed_weights())
+def test_weights_match_printed_examples(orc, row):
+    order, s, den, nums = row
+    LE, LB = orc.lagrange(order, s)
+    assert list(LB) == [n / den for n in nums]
+
+
+def _basis_by_vandermonde(nodes, s):
+    """Lagrange basis at s by solving sum_j L_j nodes_j^m = s^m exactly
+    (Gauss-Jordan on Fractions) -- a different route than the product form."""
+    n = len(nodes)
+    A = [[Fraction(nodes[j]) ** m for j in range(n)] + [Fraction(s) ** m] for m in range(n)]
+    for c in range(n):
+        piv = next(r for r in range(c, n) if A[r][c] != 0)
+        A[c], A[piv] = A[piv], A[c]
+        pv = A[c][c]
+        A[c] = [v / pv for v in A[c]]
+        for r in range(n):
+            if r != c and A[r][c] != 0:
+                f = A[r][c]
+                A[r] = [a - f * b for a, b in zip(A[r], A[c])]
+    return [A[j][n] for j in range(n)]
+
+
+@pytest.mark.parametrize("order", [1, 2, 3, 5])
+@pytest.mark.parametrize("k", [0, 1, 2, 4, 6])
+def test_weights_equal_exact_rationals(orc, order, k):
+    # B nodes at s = j - p + 1, E nodes at s = j - p + 1/2 (level times
+    # relative to (n - 1/2) dt); sub-step times s = 1/2 + (j-1)/4^k
+    nodes_B = [Fraction(j - order + 1) for j in range(order + 1)]
+    nodes_E = [Fraction(2 * (j - order) + 1, 2) for j in range(order + 1)]
+    nsub = 4 ** k
+    js = sorted({1, 2, nsub // 3 + 1, nsub // 2 + 1, nsub})
+    exact_cases = (order <= 3 and k <= 6) or (order == 5 and k <= 4)
+    for j in js:
+        s = Fraction(1, 2) + Fraction(j - 1, nsub)
+        LE, LB = orc.lagrange(order, float(s))
+        eB = _basis_by_vandermonde(nodes_B, s)
+        eE = _basis_by_vandermonde(nodes_E, s)
+        if exact_cases:
+            # numerator exact in FP64 -> one correctly rounded division
+            assert list(LB) == [float(v) for v in eB]
+            assert list(LE) == [float(v) for v in eE]
+        else:
+            np.testing.assert_allclose(LB, [float(v) for v in eB], rtol=0, atol=1e-13)
+            np.testing.assert_allclose(LE, [float(v) for v in eE], rtol=0, atol=1e-13)
+
+
+def test_weights_derived_values_at_half(orc):
+    # s = 1/2 is the time n dt: E is known there, so E's weights select E_n
+    LE, LB = orc.lagrange(3, 0.5)
+    assert list(LE) == [0.0, 0.0, 0.0, 1.0]
+    assert list(LB) == [1 / 16, -5 / 16, 15 / 16, 5 / 16]
+    LE5, LB5 = orc.lagrange(5, 0.5)
+    assert list(LB5) == [v / 256 for v in (7, -45, 126, -210, 315, 63)]
+
+
+@pytest.mark.parametrize("order", [1, 3, 5])
+def test_weights_reproduce_polynomials(orc, order):
+    rng = np.random.default_rng(3)
+    nodes_B = np.arange(order + 1) - order + 1.0
+    nodes_E = nodes_B - 0.5
+    for s in rng.uniform(0.5, 1.5, 20):
+        LE, LB = orc.lagrange(order, s)
+        for m in range(order + 1):
+            assert abs(np.dot(LB, nodes_B ** m) - s ** m) < 1e-12 * max(1, s ** m)
+            assert abs(np.dot(LE, nodes_E ** m) - s ** m) < 1e-12 * max(1, s ** m)
+
+
+@pytest.mark.parametrize("order,expected", [(1, 8.77e-4), (2, 3.67e-5), (3, 1.92e-6),
+                                            (5, 7.08e-9)])
+def test_interpolation_error_magnitude(orc, order, expected):
+    """Max error of B interpolated to n dt on a unit sinusoid at T/dt = 75
+    (the quantity of Fig. 4).  Closed form: Lagrange remainder
+    |prod_k (1/2 - s_k)| / (p+1)! (2 pi / 75)^(p+1), with s_k the B level
+    times."""
+    nodes = np.arange(order + 1) - order + 1.0
+    closed = abs(np.prod(0.5 - nodes)) / math.factorial(order + 1) * (2 * math.pi / 75) ** (order + 1)
+    assert closed == pytest.approx(expected, rel=3e-3)
+    _, LB = orc.lagrange(order, 0.5)
+    dt = 2 * math.pi / 75
+    phases = np.linspace(0, 2 * math.pi, 4001)
+    samples = np.cos(phases[:, None] + (nodes[None, :] - 0.5) * dt)
+    err = np.abs(samples @ LB - np.cos(phases)).max()
+    assert err == pytest.approx(closed, rel=0.05)
+
+
+# ---------------------------------------------------------------------------
+# Tent gather (Sec. III, Eqs. (Enp), (Bnp))
+# ---------------------------------------------------------------------------
+def _explicit_fields(E, B, lev0=0):
+    from oracle import oracle as O
+    return O.FieldSource(E=E, B=B, lev0=lev0)
+
+
+def test_tent_gather_equals_brute_force_sum(orc):
+    """Sum over every node of S(x_node - x) F_node with the tent
+    S(d) = max(0, 1 - |d| / dx); E nodes at (i+1/2) dx, B nodes at i dx."""
+    rng = np.random.default_rng(11)
+    ncells, dx, dt, x0 = 40, 0.37, 0.3, -1.25
+    order = 3
+    E = rng.standard_normal((order + 1, ncells))
+    B = rng.standard_normal((order + 1, ncells))
+    # same values on every level: the temporal weights sum to one
+    E[:] = E[0]
+    B[:] = B[0]
+    fs = _explicit_fields(E, B, lev0=0)
+    prm = orc.make_params(ncells, order, dx, dt, 0.01, x_origin=x0)
+    xE = x0 + (np.arange(ncells) + 0.5) * dx
+    xB = x0 + np.arange(ncells) * dx
+    for x in rng.uniform(x0 + 0.5 * dx, x0 + (ncells - 1) * dx, 200):
+        ref_E = np.sum(np.maximum(0, 1 - np.abs(xE - x) / dx) * E[0])
+        ref_B = np.sum(np.maximum(0, 1 - np.abs(xB - x) / dx) * B[0])
+        got_E = orc.gather(prm, fs, 0, order, 0.5, x)
+        got_B = orc.gather(prm, fs, 1, order, 0.5, x)
+        assert got_E == pytest.approx(ref_E, abs=1e-12)
+        assert got_B == pytest.approx(ref_B, abs=1e-12)
+
+
+def test_gather_exact_for_fields_linear_in_x_and_t(orc):
+    ncells, dx, dt = 64, 0.5, 0.25
+    order = 3
+    lev = np.arange(order + 1)[:, None]            # levels 0..3, gather at n = 3
+    i = np.arange(ncells)[None, :]
+    # E(x, t) = 2 x + 3 t with x = (i + 1/2) dx, t = m dt
+    E = 2 * (i + 0.5) * dx + 3 * lev * dt
+    # B(x, t) = -x + 5 t with x = i dx, t = (m + 1/2) dt
+    B = -(i * dx) + 5 * (lev + 0.5) * dt
+    fs = _explicit_fields(E, B, lev0=0)
+    prm = orc.make_params(ncells, order, dx, dt, 0.01)
+    n = order
+    for x in np.linspace(0.6 * dx, (ncells - 1.5) * dx, 37):
+        for s in (0.5, 0.75, 1.0, 1.3):
+            t = (n - 0.5 + s) * dt
+            assert orc.gather(prm, fs, 0, n, s, x) == pytest.approx(2 * x + 3 * t, abs=1e-12)
+            assert orc.gather(prm, fs, 1, n, s, x) == pytest.approx(-x + 5 * t, abs=1e-12)
+
+
+def test_gather_refuses_outside_grid(orc):
+    fs = _explicit_fields(np.zeros((4, 8)), np.zeros((4, 8)))
+    prm = orc.make_params(8, 3, 1.0, 0.5, 0.01)
+    with pytest.raises(ValueError):
+        orc.gather(prm, fs, 0, 3, 0.5, 0.49)     # E node -1 would be needed
+    with pytest.raises(ValueError):
+        orc.gather(prm, fs, 1, 3, 0.5, 7.0)      # B node 8 would be needed
+
+
+# ---------------------------------------------------------------------------
+# Boris push (Sec. III, Eqs. (p)..(x)); textbook special cases
+# ---------------------------------------------------------------------------
+def test_boris_pure_electric_kick(orc):
+    for qm, dt, E in [(-1.0, 0.1, 3.0), (1.0, 0.25, -2.0), (-1.0, 1e-3, 150.0)]:
+        p = orc.boris(qm, dt, E, 0.0, [0.3, -0.2, 0.1])
+        assert p[0] == 0.3 and p[2] == 0.1
+        assert p[1] == pytest.approx(-0.2 + qm * E * dt, rel=1e-15, abs=1e-15)
+
+
+def test_boris_pure_magnetic_rotation(orc):
+    rng = np.random.default_rng(5)
+    for _ in range(50):
+        p0 = rng.standard_normal(3) * 10
+        B, dt = rng.uniform(-200, 200), rng.uniform(1e-3, 0.1)
+        p1 = orc.boris(-1.0, dt, 0.0, B, p0)
+        g = math.sqrt(1 + p0 @ p0)
+        # |p| preserved, p_z untouched; dp/dt = q v x B turns p clockwise
+        # for q B_z > 0: angle -2 atan(q B dt / (2 gamma))
+        assert np.linalg.norm(p1) == pytest.approx(np.linalg.norm(p0), rel=1e-14)
+        assert p1[2] == p0[2]
+        ang = math.atan2(p0[0] * p1[1] - p0[1] * p1[0], p0[0] * p1[0] + p0[1] * p1[1])
+        assert ang == pytest.approx(-2 * math.atan(-1.0 * B * dt / (2 * g)), rel=1e-12, abs=1e-14)
+
+
+def _textbook_boris(qm, dt, Evec, Bvec, p):
+    """Vector-form Boris (Birdsall & Langdon) with numpy cross products."""
+    pm = p + 0.5 * qm * dt * Evec
+    g = math.sqrt(1 + pm @ pm)
+    t = 0.5 * qm * dt * Bvec / g
+    s = 2 * t / (1 + t @ t)
+    pp = pm + np.cross(pm, t)
+    return pm + np.cross(pp, s) + 0.5 * qm * dt * Evec
+
+
+def test_boris_matches_vector_textbook_form(orc):
+    rng = np.random.default_rng(9)
+    for _ in range(100):
+        p0 = rng.standard_normal(3) * 5
+        E, B, dt = rng.uniform(-50, 50), rng.uniform(-50, 50), rng.uniform(1e-3, 0.2)
+        got = orc.boris(-1.0, dt, E, B, p0)
+        ref = _textbook_boris(-1.0, dt, np.array([0, E, 0.0]), np.array([0, 0, B]), p0)
+        np.testing.assert_allclose(got, ref, rtol=1e-13, atol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# Sub-cycling decision (Sec. IV)
+# ---------------------------------------------------------------------------
+def test_decision_matches_closed_form(orc):
+    rng = np.random.default_rng(21)
+    for _ in range(2000):
+        psi_max = 10 ** rng.uniform(-4, -1)
+        ratio = 10 ** rng.uniform(-3, 4.5)
+        k_closed = max(0, math.ceil(math.log(ratio, 4)))
+        if abs(math.log(ratio, 4) - round(math.log(ratio, 4))) < 1e-9:
+            continue   # exactly on a threshold
+        k, clamped = orc.decide_k(ratio * psi_max, psi_max, 12)
+        assert k == min(k_closed, 12) and clamped == (k_closed > 12)
+
+
+def test_decision_clamps_at_k_max(orc):
+    k, clamped = orc.decide_k(1e6, 0.01, 3)
+    assert k == 3 and clamped
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 1 bookkeeping: transition push and field times
+# ---------------------------------------------------------------------------
+def _uniform_levels(order, ncells, nlev, Efun, Bfun, dt):
+    m = np.arange(nlev)[:, None]
+    E = np.broadcast_to(Efun(m * dt), (nlev, ncells)).copy()
+    B = np.broadcast_to(Bfun((m + 0.5) * dt), (nlev, ncells)).copy()
+    return E, B
+
+
+@pytest.mark.parametrize("order", [1, 3])
+def test_transition_push_keeps_momentum_time(orc, order):
+    """Uniform static E, no B: Boris is exact, so p_y = q E (t_p - t_p0)
+    with t_p = (n+1) dt - dt*/2 after step n, dt* = dt / 4^k.  Any error
+    in the (dt*_old + dt*_new)/2 transition push (Sec. IV) shows here."""
+    ncells, dx, dt, E0 = 16, 1.0, 0.1, 2.5
+    nlev = 40
+    E, B = _uniform_levels(order, ncells, nlev, lambda t: E0 + 0 * t, lambda t: 0 * t, dt)
+    fs = orc.FieldSource(E=E, B=B, lev0=0)
+    prm = orc.make_params(ncells, order, dx, dt, 0.01, x_origin=0.0)
+    ks = [0, 2, 2, 1, 3, 0, 0, 4, 1, 2, 0]
+    k_init = 1
+    st = orc.State(np.array([8.0]), k_old=np.array([k_init]))
+    n0 = order
+    tp0 = n0 * dt - dt / 4 ** k_init / 2
+    for i, k in enumerate(ks):
+        orc.push(prm, fs, st, n0 + i, 1, forced_k=np.array([[k]]))
+        tp = (n0 + i + 1) * dt - dt / 4 ** k / 2
+        assert st.py[0] == pytest.approx(-1.0 * E0 * (tp - tp0), rel=1e-13)
+
+
+@pytest.mark.parametrize("order", [1, 3])
+def test_field_time_of_each_sub_step(orc, order):
+    """E(t) = alpha t (uniform in x), no B; interpolation of order >= 1 is
+    exact for it.  Sub-step j of a step with exponent k sees the field at
+    the time of x before the sub-step, t_j = n dt + (j-1) dt*, and pushes p
+    by q E(t_j) dt_p (exact with B = 0)."""
+    ncells, dx, dt, alpha = 16, 1.0, 0.1, 0.7
+    nlev = 30
+    E, B = _uniform_levels(order, ncells, nlev, lambda t: alpha * t, lambda t: 0 * t, dt)
+    fs = orc.FieldSource(E=E, B=B, lev0=0)
+    prm = orc.make_params(ncells, order, dx, dt, 0.01)
+    for k_old, k in [(0, 0), (0, 2), (2, 1), (3, 3), (1, 0)]:
+        n = order + 2
+        st = orc.State(np.array([8.0]), k_old=np.array([k_old]))
+        orc.push(prm, fs, st, n, 1, forced_k=np.array([[k]]))
+        dto, dtn = dt / 4 ** k_old, dt / 4 ** k
+        expect = 0.0
+        for j in range(1, 4 ** k + 1):
+            tj = n * dt + (j - 1) * dtn
+            dtp = 0.5 * (dto + dtn) if j == 1 else dtn
+            expect += -1.0 * alpha * tj * dtp
+        assert st.py[0] == pytest.approx(expect, rel=1e-12, abs=1e-15)
+
+
+def test_subcycled_step_equals_fine_boris(orc):
+    """Static uniform E and B with a fixed k: one dt step is 4^k textbook
+    Boris steps of dt / 4^k (x update v dt with v = p / gamma)."""
+    order, k = 3, 2
+    ncells, dx, dt = 64, 1.0, 0.2
+    E0, B0 = 1.7, -2.3
+    E, B = _uniform_levels(order, ncells, 20, lambda t: E0 + 0 * t, lambda t: B0 + 0 * t, dt)
+    fs = orc.FieldSource(E=E, B=B, lev0=0)
+    prm = orc.make_params(ncells, order, dx, dt, 0.01)
+    p = np.array([0.4, -0.3, 0.2])
+    x = 30.0
+    st = orc.State(np.array([x]), [p[0]], [p[1]], [p[2]], k_old=np.array([k]))
+    steps = 5
+    orc.push(prm, fs, st, order, steps, forced_k=np.full((steps, 1), k, dtype=np.int8))
+    h = dt / 4 ** k
+    for _ in range(steps * 4 ** k):
+        p = _textbook_boris(-1.0, h, np.array([0, E0, 0.0]), np.array([0, 0, B0]), p)
+        x += h * p[0] / math.sqrt(1 + p @ p)
+    np.testing.assert_allclose([st.px[0], st.py[0], st.pz[0]], p, rtol=1e-12, atol=1e-13)
+    assert st.x[0] == pytest.approx(x, rel=1e-13)
+
+
+def test_forced_replay_reproduces_free_run_bitwise(orc):
+    wl = W.small_case(order=3, num=64, periods=2)
+    table, M, shift = wl.table()
+    fs = orc.FieldSource(table=table, M=M, coeffs=W.shifted_coeffs(wl.lat, shift))
+    prm = orc.make_params(wl.ncells, 3, wl.dx, wl.dt, wl.psi_max, wl.x_origin)
+    a = orc.State(wl.x0)
+    kt, _ = orc.push(prm, fs, a, 0, wl.steps, trace=True)
+    b = orc.State(wl.x0)
+    orc.push(prm, fs, b, 0, wl.steps, forced_k=kt)
+    assert np.array_equal(a.x, b.x) and np.array_equal(a.px, b.px) and np.array_equal(a.py, b.py)
+    assert kt.max() >= 2      # the cold start sub-cycles
+
+
+def test_no_subcycling_when_psi_max_is_huge(orc):
+    wl = W.small_case(order=3, num=32, periods=1)
+    table, M, shift = wl.table()
+    fs = orc.FieldSource(table=table, M=M, coeffs=W.shifted_coeffs(wl.lat, shift))
+    prm = orc.make_params(wl.ncells, 3, wl.dx, wl.dt, 1e30, wl.x_origin)
+    st = orc.State(wl.x0)
+    cnt = orc.Counters()
+    kt, _ = orc.push(prm, fs, st, 0, wl.steps, trace=True, counters=cnt)
+    assert kt.max() == 0 and cnt.n_star == 0
+    assert cnt.sub_steps == cnt.steps == wl.steps * 32
+
+
+def test_lost_particle_is_frozen_and_counted(orc):
+    ncells, dx, dt = 16, 1.0, 0.5
+    E, B = _uniform_levels(3, ncells, 40, lambda t: 0 * t + 1.0, lambda t: 0 * t, dt)
+    fs = orc.FieldSource(E=E, B=B, lev0=0)
+    prm = orc.make_params(ncells, 3, dx, dt, 1e30)
+    # electron pushed toward -x by q E < 0 along y only; give it v_x < 0
+    st = orc.State(np.array([1.0, 8.0]), px=[-50.0, 0.0])
+    cnt = orc.Counters()
+    orc.push(prm, fs, st, 3, 20, counters=cnt)
+    assert st.status[0] == 1 and st.status[1] == 0 and cnt.lost == 1
+    assert 0.0 <= st.x[0] < 0.5 * dx + 1.0
+
+
+# ---------------------------------------------------------------------------
+# The whole integrator against the plane-wave solution (Sec. II, appendix)
+# ---------------------------------------------------------------------------
+def _flat_closed_form(a0, x0):
+    """Electron at rest at x0, t = 0 in a = a0 sin(xi), xi = t - x."""
+    xi_i = -x0
+    a_i = a0 * math.sin(xi_i)
+
+    def F(u):   # antiderivative of (a0 sin u - a_i)^2
+        return a0 * a0 * (u / 2 - math.sin(2 * u) / 4) + 2 * a0 * a_i * math.cos(u) + a_i * a_i * u
+
+    def x_of(xi):
+        return x0 + 0.5 * (F(xi) - F(xi_i))
+
+    def t_of(xi):
+        return (xi - xi_i) + (x_of(xi) - x0)
+
+    def xi_at(t):
+        lo, hi = xi_i - 1.0, xi_i + 1.0
+        while t_of(lo) > t:
+            lo -= 1.0
+        while t_of(hi) < t:
+            hi += 1.0
+        for _ in range(200):
+            mid = 0.5 * (lo + hi)
+            if t_of(mid) < t:
+                lo = mid
+            else:
+                hi = mid
+        return 0.5 * (lo + hi)
+
+    def p_at(xi):
+        py = a0 * math.sin(xi) - a_i
+        return py * py / 2, py
+
+    return xi_at, x_of, t_of, p_at, a_i
+
+
+def _run_exact_start(orc, a0, x0, n_t, periods, order=3, psi_max=1e30):
+    """Integrate from p(-dt/2) of the analytic solution (k_old = 0)."""
+    lat = W.yee_lattice(n_t)
+    table, M, shift = W.plane_wave_table(lat, a0)
+    fs = orc.FieldSource(table=table, M=M, coeffs=W.shifted_coeffs(lat, shift))
+    ncells = int((x0 + periods * 2 * math.pi * 1.2) / lat.dx) + 16
+    prm = orc.make_params(ncells, order, lat.dx, lat.dt, psi_max, lat.x_origin)
+    xi_at, x_of, t_of, p_at, _ = _flat_closed_form(a0, x0)
+    px0, py0 = p_at(xi_at(-lat.dt / 2))
+    st = orc.State(np.array([x0]), [px0], [py0], [0.0], k_old=np.array([0]))
+    steps = int(round(periods * n_t))
+    orc.push(prm, fs, st, 0, steps)
+    t_end = steps * lat.dt
+    return st, x_of(xi_at(t_end))
+
+
+def test_converges_at_second_order_to_plane_wave_solution(orc):
+    x0 = 1.3
+    errs = []
+    for n_t in (150, 300, 600):
+        st, x_ref = _run_exact_start(orc, 1.0, x0, n_t, 2.0)
+        errs.append(abs(st.x[0] - x_ref))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.0 < r1 < 5.5 and 3.0 < r2 < 5.5, errs
+    assert errs[-1] < 1e-4
+
+
+def test_dephasing_invariant_and_momenta(orc):
+    """R = gamma - p_x stays 1 and p_perp follows a(xi) - a_i (Eqs.
+    (theoretical dephasing), (eq:6)) with 3rd order + sub-cycling."""
+    wl = W.make_workload("t", 16, 10.0, 75, 2048, 10, 3, 0.01, 1.0, seed=4)
+    table, M, shift = wl.table()
+    fs = orc.FieldSource(table=table, M=M, coeffs=W.shifted_coeffs(wl.lat, shift))
+    prm = orc.make_params(wl.ncells, 3, wl.dx, wl.dt, wl.psi_max, wl.x_origin)
+    st = orc.State(wl.x0)
+    worst_R = 0.0
+    for n in range(wl.steps):
+        orc.push(prm, fs, st, n, 1)
+        worst_R = max(worst_R, np.abs(st.gamma() - st.px - 1).max())
+    assert worst_R < 5e-3
+    assert np.all(st.pz == 0.0)
+    # transverse canonical momentum: p_y - a(xi) stays -a_i; at the momentum
+    # time the phase is about t_p - x
+    for i in range(wl.num):
+        _, _, _, _, a_i = _flat_closed_form(wl.a0, wl.x0[i])
+        dtk = wl.dt / 4 ** int(0)
+        tp = wl.steps * wl.dt - 0.5 * dtk
+        xi = tp - (st.x[i] - 0.5 * dtk * st.px[i] / st.gamma()[i])
+        assert st.py[i] - wl.a0 * math.sin(xi) == pytest.approx(-a_i, abs=0.05 * wl.a0)
+
+
+def test_stopping_point_times_match_closed_form(orc):
+    """Stopping points (p = 0, Sec. II) occur where a(xi) returns to a_i;
+    the time of the gamma minimum must match t(xi_s) of the solution."""
+    a0, n_t = 10.0, 75
+    x0 = 0.3          # first stopping points near 24.8 and 30.4 periods
+    lat = W.yee_lattice(n_t)
+    table, M, shift = W.plane_wave_table(lat, a0)
+    fs = orc.FieldSource(table=table, M=M, coeffs=W.shifted_coeffs(lat, shift))
+    prm = orc.make_params(4096, 3, lat.dx, lat.dt, 0.01, lat.x_origin)
+    st = orc.State(np.array([x0]))
+    gam = []
+    steps = 35 * n_t
+    for n in range(steps):
+        orc.push(prm, fs, st, n, 1)
+        gam.append(st.gamma()[0])
+    gam = np.array(gam)
+    xi_at, x_of, t_of, p_at, a_i = _flat_closed_form(a0, x0)
+    xi_i = -x0
+    # next stopping points after the start: pi - xi_i + 2 pi m and xi_i + 2 pi m
+    cands = sorted(v for m in range(0, 3) for v in (math.pi - xi_i + 2 * math.pi * m,
+                                                    xi_i + 2 * math.pi * (m + 1)) if v > xi_i + 0.1)
+    found = 0
+    for xs in cands:
+        ts = t_of(xs)
+        n = int(round(ts / lat.dt))
+        if n + 5 >= steps:
+            break
+        w = slice(max(0, n - 40), n + 40)
+        n_min = w.start + int(np.argmin(gam[w]))
+        assert gam[n_min] < 1.05
+        assert abs(n_min * lat.dt - ts) < 3 * lat.dt
+        found += 1
+    assert found >= 2
+
+
+def test_third_order_with_subcycling_beats_first_order(orc):
+    """Sec. VI: with sub-cycling, 3rd-order temporal interpolation reduces
+    the dephasing error by much more than an order of magnitude compared
+    with 1st order, and sub-cycling helps the 3rd-order scheme."""
+    def eps(order, psi_max, a0):
+        wl = W.make_workload("t", 32, a0, 75, 2048, 12, order, psi_max, 1.0, seed=8)
+        table, M, shift = wl.table()
+        fs = orc.FieldSource(table=table, M=M, coeffs=W.shifted_coeffs(wl.lat, shift))
+        prm = orc.make_params(wl.ncells, order, wl.dx, wl.dt, psi_max, wl.x_origin)
+        st = orc.State(wl.x0)
+        worst = 0.0
+        for n in range(wl.steps):
+            orc.push(prm, fs, st, n, 1)
+            worst = max(worst, np.abs(st.gamma() - st.px - 1).max())
+        return worst
+    e1 = eps(1, 0.01, 50.0)
+    e3 = eps(3, 0.01, 50.0)
+    e3_nosub = eps(3, 1e30, 50.0)
+    assert e3 < e1 / 10
+    assert e3 < e3_nosub
+
+
+def test_counters_n_and_n_star(orc):
+    wl = W.small_case(order=3, num=128, periods=3)
+    table, M, shift = wl.table()
+    fs = orc.FieldSource(table=table, M=M, coeffs=W.shifted_coeffs(wl.lat, shift))
+    prm = orc.make_params(wl.ncells, 3, wl.dx, wl.dt, wl.psi_max, wl.x_origin)
+    st = orc.State(wl.x0)
+    cnt = orc.Counters()
+    kt, _ = orc.push(prm, fs, st, 0, wl.steps, trace=True, counters=cnt)
+    assert cnt.steps == wl.steps * wl.num
+    assert cnt.sub_steps == int(np.sum(4 ** kt.astype(np.int64)))
+    assert cnt.n_star == int(np.sum(np.where(kt > 0, 4 ** kt.astype(np.int64), 0)))
+    assert list(cnt.steps_by_k)[:9] == [int(np.sum(kt == k)) for k in range(9)]
