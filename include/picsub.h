@@ -1,0 +1,187 @@
+/*
+ * picsub.h -- C ABI of the MI355X sub-cycled Boris particle push.
+ *
+ * The library advances test electrons through prescribed 1D Yee-grid
+ * fields with the relativistic Boris pusher, adaptive per-particle
+ * sub-cycling (dt* = dt / 4^k, k from the Psi_max rotation criterion) and
+ * order-p temporal Lagrange interpolation of E_y and B_z, following
+ * Tangtartharakul, Chen & Arefiev, arXiv:2102.10983:
+ *   Sec. III  Yee staggering (Eqs. (Ey), (Bz)), tent gather (Eqs. (Enp),
+ *             (Bnp)) and the Boris push (Eqs. (p)..(x));
+ *   Sec. IV   the Psi_max criterion, the leapfrog-consistent transition
+ *             push and Algorithm 1 ("Sub-Cycling");
+ *   Sec. VI   Lagrange interpolation during sub-cycling
+ *             (Eqs. (lagrange1-2)..(lagrange2-3));
+ *   Sec. VII  the step counters N and N* (delta_steps).
+ *
+ * Conventions
+ *   Units: t in 1/omega, x in c/omega, p in m c, E and B in
+ *   m omega c / |e|; qm = charge / mass in electron units (-1: electron).
+ *   Field level m: E_y at t = m dt on nodes x_origin + (i + 1/2) dx and
+ *   B_z at t = (m + 1/2) dt on nodes x_origin + i dx, i = 0..ncells-1.
+ *   Particle state at step n: x at t = n dt; p at t = n dt - dt*_old / 2
+ *   where dt*_old = dt / 4^k_old (k_old < 0: p lags x by half of the
+ *   sub-step chosen at the next step, e.g. an electron at rest).
+ *   Sub-step j (1..4^k) of the step at level n uses the fields at the
+ *   time of x before that sub-step, s_j = 1/2 + (j-1) / 4^k in units of dt
+ *   after (n - 1/2) dt; the first sub-step's momentum push uses
+ *   (dt*_old + dt*_new) / 2 (Sec. IV).
+ *
+ * Ownership and errors
+ *   Every call returns pic_status; nothing throws or aborts across the
+ *   ABI.  pic_last_error() returns a message for the last failure on a
+ *   context (the HIP error string for PIC_E_DEVICE).  The library owns the
+ *   device state it allocates in pic_create; the caller owns every array it
+ *   passes in or receives.  Work is enqueued on the stream given to
+ *   pic_create; calls with PIC_MEM_HOST buffers synchronise that stream,
+ *   calls with PIC_MEM_DEVICE buffers are asynchronous and the caller keeps
+ *   the buffers valid until the stream has passed them.  A context is not
+ *   thread-safe; distinct contexts are independent.  A particle whose
+ *   tent nodes leave the grid is frozen and flagged PIC_PARTICLE_LOST; it
+ *   is not an error.
+ */
+#ifndef PICSUB_H
+#define PICSUB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PIC_OK = 0,
+    PIC_E_ARG = 1,     /* invalid argument (null pointer, size, parameter) */
+    PIC_E_DEVICE = 2,  /* a HIP call failed */
+    PIC_E_NOMEM = 3,   /* device or host allocation failed */
+    PIC_E_LEVEL = 4,   /* a field level the push needs is not in the ring */
+    PIC_E_STATE = 5    /* call out of order (e.g. push before particles) */
+} pic_status;
+
+typedef enum { PIC_MEM_HOST = 0, PIC_MEM_DEVICE = 1 } pic_mem;
+
+/* arithmetic of the push */
+typedef enum {
+    PIC_FP64 = 0,       /* everything in FP64 */
+    PIC_FP32_COMP = 1   /* FP32 bulk with compensated x and p; FP64
+                           weights, decision and sub-cycled steps */
+} pic_precision;
+
+/* how particles are grouped onto wavefronts for the sub-step loop */
+typedef enum {
+    PIC_BIN_NONE = 0,    /* one particle per lane, no regrouping */
+    PIC_BIN_BALLOT = 1,  /* per-step compaction by k inside a workgroup */
+    PIC_BIN_LEARNED = 2  /* BALLOT plus an MLP pre-partition by predicted k */
+} pic_binning;
+
+#define PIC_PARTICLE_LIVE 0u
+#define PIC_PARTICLE_LOST 1u
+
+#define PIC_KHIST 16
+#define PIC_K_MAX_LIMIT 8
+
+typedef struct {
+    int32_t ncells;      /* nodes per field, >= 2 */
+    int32_t order;       /* temporal interpolation order p: 1, 3 or 5 */
+    int32_t ring_depth;  /* stored levels, >= order + 1 */
+    int32_t k_max;       /* cap of k, 0..PIC_K_MAX_LIMIT */
+    int32_t precision;   /* pic_precision */
+    int32_t binning;     /* pic_binning */
+    double x_origin;     /* x of B node 0 */
+    double dx;           /* cell size, > 0 */
+    double dt;           /* time step, > 0 */
+    double qm;           /* charge / mass, nonzero */
+    double psi_max;      /* maximum rotation per sub-step, > 0 (Sec. IV) */
+} pic_params;
+
+typedef struct {
+    uint64_t steps;       /* N: particle-steps of size dt taken */
+    uint64_t sub_steps;   /* Boris sub-steps performed (sum of 4^k) */
+    uint64_t n_star;      /* N*: sub-steps with dt* < dt (Sec. VII) */
+    uint64_t clamps;      /* decisions that hit k_max unmet */
+    uint64_t lost;        /* particles flagged lost */
+    uint64_t steps_by_k[PIC_KHIST];
+    uint64_t sub_steps_by_k[PIC_KHIST];
+} pic_counters;
+
+typedef struct pic_ctx pic_ctx;
+
+/* Create a context for np particles with parameters *prm; all work goes
+ * to hip_stream (a hipStream_t, NULL for the default stream) on the
+ * current device.  Validates the parameters (PIC_E_ARG), allocates the
+ * particle store, the field ring of prm->ring_depth levels and the table
+ * of Lagrange weights for every (k, j) (Eqs. (lagrange2-2),
+ * (lagrange2-3)).  On success *out owns the device memory. */
+pic_status pic_create(const pic_params *prm, int64_t np, void *hip_stream,
+                      pic_ctx **out);
+
+/* Release everything a context owns (synchronises its stream). */
+pic_status pic_destroy(pic_ctx *ctx);
+
+/* Message for the last failure on ctx ("" if none); valid until the next
+ * call on ctx. */
+const char *pic_last_error(const pic_ctx *ctx);
+
+/* Load the particle state: x, px, py, pz (np doubles each, the time
+ * convention above) and k_old (np int8; NULL means -1 for all).  Resets
+ * the status flags and the counters.  Particles are reordered internally
+ * by position (cell index); every per-particle output is returned in the
+ * caller's original order. */
+pic_status pic_particles_set(pic_ctx *ctx, pic_mem mem, const double *x,
+                             const double *px, const double *py,
+                             const double *pz, const int8_t *k_old);
+
+/* Store field level n (Sec. III staggering): Ey[i] = E_y(x_origin +
+ * (i + 1/2) dx, n dt), Bz[i] = B_z(x_origin + i dx, (n + 1/2) dt), ncells
+ * doubles each, into ring slot n mod ring_depth. */
+pic_status pic_fields_load(pic_ctx *ctx, int64_t n, pic_mem mem,
+                           const double *Ey, const double *Bz);
+
+/* Fill levels n_first .. n_first + count - 1 on the device from a phase
+ * table: Ey[i] = table[(aE m + bE i + cE) mod M], Bz[i] = table[(aB m +
+ * bB i + cB) mod M] for level m.  table is a device array of M doubles.
+ * This samples prescribed fields ("perfectly propagating PIC", Sec. III)
+ * without host traffic.  count <= ring_depth. */
+pic_status pic_fields_load_lattice(pic_ctx *ctx, int64_t n_first,
+                                   int32_t count, const double *table,
+                                   int64_t M, int64_t aE, int64_t bE,
+                                   int64_t cE, int64_t aB, int64_t bB,
+                                   int64_t cB);
+
+/* Advance every live particle from x at n dt to (n + S) dt: S steps of
+ * Algorithm 1 (Sec. IV) with order-p interpolation (Sec. VI).  Requires
+ * levels n - order .. n + S - 1 in the ring (PIC_E_LEVEL otherwise, and
+ * nothing is enqueued).  Asynchronous on the context's stream. */
+pic_status pic_push_subcycled(pic_ctx *ctx, int64_t n, int32_t S);
+
+/* Record the sub-cycling exponent k chosen at steps n_first ..
+ * n_first + steps - 1 for the particles with caller index in
+ * [first, first + count) into buf[(n - n_first) * count + (index - first)]
+ * (device int8 array of steps * count entries owned by the caller; -1
+ * where the particle was not live).  buf == NULL switches recording off.
+ * Used to compare decisions and to collect training labels. */
+pic_status pic_ktrace_set(pic_ctx *ctx, int8_t *buf, int64_t n_first,
+                          int32_t steps, int64_t first, int64_t count);
+
+/* Read the state: gamma = sqrt(1 + |p|^2) of the stored momentum, p, x,
+ * the last k, the status flags (np entries each, caller order; any
+ * pointer may be NULL) and the counters (may be NULL).  With
+ * PIC_MEM_HOST the call synchronises the stream. */
+pic_status pic_diag(pic_ctx *ctx, pic_mem mem, double *gamma, double *px,
+                    double *py, double *pz, double *x, int8_t *k_last,
+                    uint8_t *status, pic_counters *cnt);
+
+/* Reset the counters to zero (asynchronous). */
+pic_status pic_counters_reset(pic_ctx *ctx);
+
+/* Tuning knobs of the push launch (0 keeps the current value):
+ * block = threads per workgroup (64..1024, multiple of 64);
+ * tile  = particles per compaction tile (multiple of block). */
+pic_status pic_tune_set(pic_ctx *ctx, int32_t block, int32_t tile);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

@@ -1,0 +1,254 @@
+"""Python binding of libpicsub (the C ABI declared in include/picsub.h).
+
+Argument marshalling only: every step of the push runs in the library's HIP
+kernels.  PyTorch supplies device memory and the stream.  There is no CPU
+fallback: if libpicsub.so is missing or no GPU is present, the calls raise.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libpicsub.so")
+
+PIC_KHIST = 16
+PIC_K_MAX_LIMIT = 8
+STATUS = {0: "PIC_OK", 1: "PIC_E_ARG", 2: "PIC_E_DEVICE", 3: "PIC_E_NOMEM",
+          4: "PIC_E_LEVEL", 5: "PIC_E_STATE"}
+PRECISION = {"fp64": 0, "fp32c": 1}
+BINNING = {"none": 0, "ballot": 1, "learned": 2}
+MEM_HOST, MEM_DEVICE = 0, 1
+
+# every symbol the header declares
+EXPORTS = ("pic_create", "pic_destroy", "pic_last_error", "pic_particles_set",
+           "pic_fields_load", "pic_fields_load_lattice", "pic_push_subcycled",
+           "pic_ktrace_set", "pic_diag", "pic_counters_reset", "pic_tune_set")
+
+
+class PicError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Params(C.Structure):
+    _fields_ = [("ncells", C.c_int32), ("order", C.c_int32), ("ring_depth", C.c_int32),
+                ("k_max", C.c_int32), ("precision", C.c_int32), ("binning", C.c_int32),
+                ("x_origin", C.c_double), ("dx", C.c_double), ("dt", C.c_double),
+                ("qm", C.c_double), ("psi_max", C.c_double)]
+
+
+class Counters(C.Structure):
+    _fields_ = [("steps", C.c_uint64), ("sub_steps", C.c_uint64), ("n_star", C.c_uint64),
+                ("clamps", C.c_uint64), ("lost", C.c_uint64),
+                ("steps_by_k", C.c_uint64 * PIC_KHIST),
+                ("sub_steps_by_k", C.c_uint64 * PIC_KHIST)]
+
+    def as_dict(self):
+        return {"steps": self.steps, "sub_steps": self.sub_steps, "n_star": self.n_star,
+                "clamps": self.clamps, "lost": self.lost,
+                "steps_by_k": list(self.steps_by_k),
+                "sub_steps_by_k": list(self.sub_steps_by_k)}
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> C.CDLL:
+    """Load libpicsub.so and declare the signatures (no GPU needed)."""
+    global _lib
+    if _lib is not None and path == LIB_PATH:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError(
+            f"{path} is not built; run `python -c 'import __graft_entry__ as g; g.build()'`")
+    L = C.CDLL(path)
+    vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    sig = {
+        "pic_create": ([C.POINTER(Params), i64, vp, C.POINTER(vp)], C.c_int),
+        "pic_destroy": ([vp], C.c_int),
+        "pic_last_error": ([vp], C.c_char_p),
+        "pic_particles_set": ([vp, C.c_int, vp, vp, vp, vp, vp], C.c_int),
+        "pic_fields_load": ([vp, i64, C.c_int, vp, vp], C.c_int),
+        "pic_fields_load_lattice": ([vp, i64, i32, vp, i64, i64, i64, i64, i64, i64, i64],
+                                    C.c_int),
+        "pic_push_subcycled": ([vp, i64, i32], C.c_int),
+        "pic_ktrace_set": ([vp, vp, i64, i32, i64, i64], C.c_int),
+        "pic_diag": ([vp, C.c_int, vp, vp, vp, vp, vp, vp, vp, C.POINTER(Counters)], C.c_int),
+        "pic_counters_reset": ([vp], C.c_int),
+        "pic_tune_set": ([vp, i32, i32], C.c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    if path == LIB_PATH:
+        _lib = L
+    return L
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("libpicsub needs a ROCm GPU; none is visible")
+    return torch
+
+
+def _dev_ptr(t, dtype, n=None):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a device tensor")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"expected a contiguous {dtype} tensor, got {t.dtype}")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"expected {n} elements, got {t.numel()}")
+    return t.data_ptr()
+
+
+class Pusher:
+    """One context of the C ABI: np particles, a field ring, a stream."""
+
+    def __init__(self, *, num: int, ncells: int, order: int, dx: float, dt: float,
+                 psi_max: float, x_origin: float = 0.0, qm: float = -1.0, k_max: int = 8,
+                 ring_depth: int | None = None, precision: str = "fp64",
+                 binning: str = "none", stream=None):
+        torch = _torch()
+        self._lib = load_library()
+        self.num = int(num)
+        self.order = int(order)
+        self.ring_depth = int(ring_depth or (order + 1))
+        self.prm = Params(ncells=ncells, order=order, ring_depth=self.ring_depth, k_max=k_max,
+                          precision=PRECISION[precision], binning=BINNING[binning],
+                          x_origin=x_origin, dx=dx, dt=dt, qm=qm, psi_max=psi_max)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self._ctx = C.c_void_p()
+        st = self._lib.pic_create(C.byref(self.prm), self.num, C.c_void_p(self.stream.cuda_stream),
+                                  C.byref(self._ctx))
+        if st != 0:
+            msg = self._err()
+            if self._ctx:
+                self._lib.pic_destroy(self._ctx)
+                self._ctx = C.c_void_p()
+            raise PicError(st, msg)
+        self._keep = []
+
+    # -- helpers ---------------------------------------------------------
+    def _err(self) -> str:
+        if not self._ctx:
+            return "context creation failed"
+        m = self._lib.pic_last_error(self._ctx)
+        return m.decode() if m else ""
+
+    def _check(self, st: int):
+        if st != 0:
+            raise PicError(st, self._err())
+
+    def close(self):
+        if self._ctx:
+            self._lib.pic_destroy(self._ctx)
+            self._ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- calls -----------------------------------------------------------
+    def particles_set(self, x, px, py, pz, k_old=None):
+        """Device tensors (float64, int8) or host numpy arrays."""
+        torch = _torch()
+        n = self.num
+        if isinstance(x, torch.Tensor):
+            ptrs = [_dev_ptr(a, torch.float64, n) for a in (x, px, py, pz)]
+            kp = None if k_old is None else _dev_ptr(k_old, torch.int8, n)
+            self._check(self._lib.pic_particles_set(self._ctx, MEM_DEVICE, *ptrs, kp))
+        else:
+            arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (x, px, py, pz)]
+            for a in arrs:
+                if a.size != n:
+                    raise ValueError("wrong particle count")
+            ka = None if k_old is None else np.ascontiguousarray(k_old, dtype=np.int8)
+            self._check(self._lib.pic_particles_set(
+                self._ctx, MEM_HOST, *[a.ctypes.data for a in arrs],
+                None if ka is None else ka.ctypes.data))
+
+    def fields_load(self, n: int, Ey, Bz):
+        torch = _torch()
+        if isinstance(Ey, torch.Tensor):
+            nc = self.prm.ncells
+            self._check(self._lib.pic_fields_load(self._ctx, n, MEM_DEVICE,
+                                                  _dev_ptr(Ey, torch.float64, nc),
+                                                  _dev_ptr(Bz, torch.float64, nc)))
+        else:
+            E = np.ascontiguousarray(Ey, dtype=np.float64)
+            B = np.ascontiguousarray(Bz, dtype=np.float64)
+            if E.size != self.prm.ncells or B.size != self.prm.ncells:
+                raise ValueError("wrong field length")
+            self._check(self._lib.pic_fields_load(self._ctx, n, MEM_HOST, E.ctypes.data,
+                                                  B.ctypes.data))
+
+    def fields_load_lattice(self, n_first: int, count: int, table, M: int, coeffs):
+        torch = _torch()
+        tp = _dev_ptr(table, torch.float64)
+        if table.numel() < M:
+            raise ValueError("table shorter than M")
+        self._check(self._lib.pic_fields_load_lattice(self._ctx, n_first, count, tp, M,
+                                                      *[int(c) for c in coeffs]))
+
+    def push(self, n: int, S: int = 1):
+        self._check(self._lib.pic_push_subcycled(self._ctx, n, S))
+
+    def ktrace_set(self, buf, n_first: int = 0, first: int = 0):
+        """Record k for caller indices [first, first + buf.shape[1]) at steps
+        n_first .. n_first + buf.shape[0] - 1 into the int8 device tensor buf."""
+        torch = _torch()
+        if buf is None:
+            self._check(self._lib.pic_ktrace_set(self._ctx, None, 0, 0, 0, 0))
+            return
+        if buf.dim() != 2:
+            raise ValueError("k trace buffer must be [steps, count]")
+        self._check(self._lib.pic_ktrace_set(self._ctx, _dev_ptr(buf, torch.int8), n_first,
+                                             buf.shape[0], first, buf.shape[1]))
+        self._keep = [buf]
+
+    def counters_reset(self):
+        self._check(self._lib.pic_counters_reset(self._ctx))
+
+    def tune(self, block: int = 0, tile: int = 0):
+        self._check(self._lib.pic_tune_set(self._ctx, block, tile))
+
+    def counters(self) -> dict:
+        c = Counters()
+        self._check(self._lib.pic_diag(self._ctx, MEM_HOST, None, None, None, None, None,
+                                       None, None, C.byref(c)))
+        return c.as_dict()
+
+    def diag(self) -> dict:
+        """Host copies of gamma, px, py, pz, x, k_last, status (caller order)."""
+        n = self.num
+        out = {k: np.empty(n) for k in ("gamma", "px", "py", "pz", "x")}
+        out["k_last"] = np.empty(n, dtype=np.int8)
+        out["status"] = np.empty(n, dtype=np.uint8)
+        c = Counters()
+        self._check(self._lib.pic_diag(
+            self._ctx, MEM_HOST, *[out[k].ctypes.data for k in ("gamma", "px", "py", "pz", "x")],
+            out["k_last"].ctypes.data, out["status"].ctypes.data, C.byref(c)))
+        out["counters"] = c.as_dict()
+        return out
+
+    def diag_device(self, out: dict):
+        """Write into caller-owned device tensors (any key may be missing)."""
+        torch = _torch()
+        n = self.num
+
+        def p(key, dt):
+            return _dev_ptr(out[key], dt, n) if key in out else None
+        self._check(self._lib.pic_diag(
+            self._ctx, MEM_DEVICE, p("gamma", torch.float64), p("px", torch.float64),
+            p("py", torch.float64), p("pz", torch.float64), p("x", torch.float64),
+            p("k_last", torch.int8), p("status", torch.uint8), None))

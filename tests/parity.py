@@ -1,0 +1,86 @@
+"""Parity helpers: run the oracle on the same seeded inputs and compare.
+
+Comparison protocol for the sub-cycling decision (several results can be
+correct when psi0 sits within rounding of a threshold psi_max 4^k):
+per-particle k traces are compared first; particles whose traces agree
+must meet the tolerance directly; particles whose traces differ are
+replayed by the oracle with the device's k sequence forced and must then
+meet the tolerance, and every such flip must sit within rounding of a
+threshold.
+"""
+
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from oracle import oracle as O
+from paper_2102_10983_amd import workloads as W
+
+
+def oracle_fields(wl: W.Workload):
+    table, M, shift = wl.table()
+    return O.FieldSource(table=table, M=M, coeffs=W.shifted_coeffs(wl.lat, shift))
+
+
+def oracle_params(wl: W.Workload, order=None, psi_max=None, k_max=8):
+    return O.make_params(wl.ncells, wl.order if order is None else order, wl.dx, wl.dt,
+                         wl.psi_max if psi_max is None else psi_max, wl.x_origin, k_max=k_max)
+
+
+def oracle_run(wl, steps, idx=None, order=None, psi_max=None, trace=False, forced_k=None,
+               k_old=None, threads=0):
+    idx = np.arange(wl.num) if idx is None else np.asarray(idx)
+    st = O.State(wl.x0[idx], wl.p0[0][idx], wl.p0[1][idx], wl.p0[2][idx],
+                 k_old=None if k_old is None else np.asarray(k_old)[idx])
+    cnt = O.Counters()
+    kt, pt = O.push(oracle_params(wl, order, psi_max), oracle_fields(wl), st, 0, steps,
+                    trace=trace, psi_trace=trace, forced_k=forced_k, counters=cnt,
+                    threads=threads)
+    return st, cnt, kt, pt
+
+
+def errors(gx, gpx, gpy, gpz, st: O.State, x0):
+    """e_p = |p - p_ref| / max(|p_ref|, 1); e_x = |x - x_ref| / max(|x_ref - x0|, 2 pi)."""
+    dp = np.sqrt((gpx - st.px) ** 2 + (gpy - st.py) ** 2 + (gpz - st.pz) ** 2)
+    pref = np.sqrt(st.px ** 2 + st.py ** 2 + st.pz ** 2)
+    e_p = dp / np.maximum(pref, 1.0)
+    e_x = np.abs(gx - st.x) / np.maximum(np.abs(st.x - x0), 2 * math.pi)
+    return e_p, e_x
+
+
+def compare(wl, steps, gdiag, idx, tol, g_ktrace=None, order=None, psi_max=None):
+    """Compare device results (caller order, full arrays) on particles idx.
+
+    Returns a dict of statistics; raises AssertionError on a violation."""
+    idx = np.asarray(idx)
+    st, cnt, kt, pt = oracle_run(wl, steps, idx, order=order, psi_max=psi_max,
+                                 trace=g_ktrace is not None)
+    gx, gpx, gpy, gpz = (gdiag[k][idx] for k in ("x", "px", "py", "pz"))
+    out = {"n": len(idx), "flips": 0, "bitwise": 0}
+    same = np.ones(len(idx), dtype=bool)
+    if g_ktrace is not None:
+        gk = g_ktrace[:, idx]
+        same = np.all(gk == kt, axis=0)
+        out["flips"] = int((~same).sum())
+        if out["flips"]:
+            # every flip must sit at a threshold: psi0 / psi_max within
+            # rounding of 4^k at the first differing step
+            for c in np.nonzero(~same)[0]:
+                s0 = int(np.argmax(gk[:, c] != kt[:, c]))
+                r = pt[s0, c]
+                kk = max(int(gk[s0, c]), int(kt[s0, c]))
+                assert r > 0 and abs(r / 4.0 ** (kk - 1) - 1) < 1e-9, (c, s0, r, gk[s0, c], kt[s0, c])
+            fst, _, _, _ = oracle_run(wl, steps, idx[~same], order=order, psi_max=psi_max,
+                                      forced_k=np.ascontiguousarray(gk[:, ~same]))
+            st.x[~same], st.px[~same], st.py[~same], st.pz[~same] = fst.x, fst.px, fst.py, fst.pz
+            st.status[~same] = fst.status
+    e_p, e_x = errors(gx, gpx, gpy, gpz, st, wl.x0[idx])
+    out["max_e_p"] = float(e_p.max()) if len(idx) else 0.0
+    out["max_e_x"] = float(e_x.max()) if len(idx) else 0.0
+    out["bitwise"] = int(np.sum((gx == st.x) & (gpx == st.px) & (gpy == st.py) & (gpz == st.pz)))
+    assert np.array_equal(gdiag["status"][idx], st.status), "status flags differ"
+    assert out["max_e_p"] <= tol and out["max_e_x"] <= tol, out
+    out["oracle_counters"] = cnt
+    return out

@@ -1,0 +1,206 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerance for the FP64 path: 1e-12 relative on p and x
+(e_p = |p - p_ref| / max(|p_ref|, 1), e_x = |x - x_ref| / max(|x_ref - x0|,
+2 pi)), with the k-trace protocol of tests/parity.py.
+"""
+
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2102_10983_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+TOL64 = 1e-12
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def runner(torch_gpu):
+    from paper_2102_10983_amd import runner as R
+    return R
+
+
+def _ktrace(torch, run, steps):
+    buf = torch.full((steps, run.wl.num), -2, dtype=torch.int8, device="cuda")
+    run.pusher.ktrace_set(buf, 0)
+    return buf
+
+
+def _gpu_full(torch, runner, wl, steps, S, order=None, psi_max=None, trace=True):
+    run = runner.DeviceRun(wl, S=S, order=order, psi_max=psi_max)
+    run.reset()
+    buf = _ktrace(torch, run, steps) if trace else None
+    run.advance(steps)
+    d = run.diag()
+    kt = buf.cpu().numpy() if trace else None
+    run.close()
+    return d, kt
+
+
+def test_native_library_is_loaded(torch_gpu, runner):
+    wl = W.small_case(order=3, num=64, periods=0.1)
+    run = runner.DeviceRun(wl)
+    run.close()
+    maps = open("/proc/self/maps").read()
+    assert "libpicsub.so" in maps
+
+
+@pytest.mark.parametrize("order", [1, 3])
+def test_single_step(torch_gpu, runner, order):
+    _say(f"single step order={order}")
+    wl = W.small_case(order=order, num=1024, periods=1)
+    d, kt = _gpu_full(torch_gpu, runner, wl, 1, 1)
+    from parity import compare
+    res = compare(wl, 1, d, np.arange(wl.num), TOL64, g_ktrace=kt)
+    _say(res)
+    assert res["flips"] == 0
+
+
+@pytest.mark.parametrize("order,S", [(1, 1), (3, 1), (3, 16), (1, 75)])
+def test_small_case_full_run(torch_gpu, runner, order, S):
+    """1024 electrons, a0 = 10, T/dt = 75, 2048 cells, 20 periods."""
+    _say(f"small case order={order} S={S}")
+    wl = W.small_case(order=order)
+    d, kt = _gpu_full(torch_gpu, runner, wl, wl.steps, S)
+    from parity import compare
+    res = compare(wl, wl.steps, d, np.arange(wl.num), TOL64, g_ktrace=kt)
+    _say({k: v for k, v in res.items() if k != "oracle_counters"})
+    c = res["oracle_counters"]
+    if res["flips"] == 0:
+        g = d["counters"]
+        assert g["steps"] == c.steps and g["sub_steps"] == c.sub_steps
+        assert g["n_star"] == c.n_star and g["steps_by_k"] == list(c.steps_by_k)
+    assert kt.min() >= 0 and kt.max() >= 2
+
+
+def test_ragged_sizes(torch_gpu, runner):
+    from parity import compare
+    for num in (1, 63, 65, 1000, 4099):
+        _say(f"ragged num={num}")
+        wl = W.make_workload("r", num, 30.0, 75, 2048, 2, 3, 0.01, 1.0, seed=num)
+        d, kt = _gpu_full(torch_gpu, runner, wl, wl.steps, 10)
+        compare(wl, wl.steps, d, np.arange(num), TOL64, g_ktrace=kt)
+
+
+def test_empty_particle_set(torch_gpu, runner):
+    wl = W.small_case(order=3, num=0, periods=0.2)
+    run = runner.DeviceRun(wl, S=5)
+    run.reset()
+    run.advance(wl.steps)
+    d = run.diag()
+    assert d["counters"]["steps"] == 0 and d["x"].size == 0
+    run.close()
+
+
+def test_explicit_levels_equal_lattice_levels(torch_gpu, runner):
+    """pic_fields_load (host and device arrays) gives bitwise the same push
+    as the on-device lattice sampler."""
+    torch = torch_gpu
+    from paper_2102_10983_amd import picsub
+    wl = W.small_case(order=3, num=512, periods=2)
+    d_lat, _ = _gpu_full(torch, runner, wl, wl.steps, 1, trace=False)
+    table, M, shift = wl.table()
+    for mem in ("host", "device"):
+        pu = picsub.Pusher(num=wl.num, ncells=wl.ncells, order=3, dx=wl.dx, dt=wl.dt,
+                           psi_max=wl.psi_max, x_origin=wl.x_origin, ring_depth=4)
+        pu.particles_set(wl.x0, *wl.p0)
+        for n in range(-3, wl.steps):
+            E, B = W.sample_levels(wl.lat, table, M, shift, wl.ncells, n, 1)
+            if mem == "device":
+                pu.fields_load(n, torch.from_numpy(E[0]).cuda(), torch.from_numpy(B[0]).cuda())
+            else:
+                pu.fields_load(n, E[0], B[0])
+            if n >= 0:
+                pu.push(n, 1)
+        d = pu.diag()
+        pu.close()
+        for k in ("x", "px", "py", "pz"):
+            assert np.array_equal(d[k], d_lat[k]), (mem, k)
+
+
+def test_lost_particles_match_oracle(torch_gpu, runner):
+    """Electrons started next to the right edge leave the grid; they are
+    frozen and flagged exactly where the oracle freezes them."""
+    from parity import compare
+    wl = W.make_workload("edge", 256, 30.0, 75, 160, 3, 3, 0.01, 1.0, seed=3)
+    wl.x0[:] = wl.x_origin + (150 + 8 * np.arange(256) / 256.0) * wl.dx
+    wl.x0[::7] = wl.x_origin + 0.25 * wl.dx        # outside on the left from the start
+    d, kt = _gpu_full(torch_gpu, runner, wl, wl.steps, 25)
+    res = compare(wl, wl.steps, d, np.arange(wl.num), TOL64, g_ktrace=kt)
+    assert d["counters"]["lost"] == int((d["status"] != 0).sum()) > 40
+    _say(res["oracle_counters"].lost, d["counters"]["lost"])
+    assert res["oracle_counters"].lost == d["counters"]["lost"]
+
+
+def test_error_codes(torch_gpu):
+    from paper_2102_10983_amd import picsub
+    with pytest.raises(picsub.PicError) as e:
+        picsub.Pusher(num=4, ncells=16, order=2, dx=1.0, dt=0.5, psi_max=0.01)
+    assert e.value.status == 1
+    with pytest.raises(picsub.PicError) as e:
+        picsub.Pusher(num=4, ncells=16, order=3, dx=1.0, dt=0.5, psi_max=0.01, ring_depth=3)
+    assert e.value.status == 1
+    pu = picsub.Pusher(num=4, ncells=16, order=3, dx=1.0, dt=0.5, psi_max=0.01, ring_depth=5)
+    with pytest.raises(picsub.PicError) as e:
+        pu.push(0, 1)
+    assert e.value.status == 5          # particles not loaded
+    pu.particles_set(np.full(4, 8.0), np.zeros(4), np.zeros(4), np.zeros(4))
+    z = np.zeros(16)
+    for n in (-3, -2, -1):
+        pu.fields_load(n, z, z)
+    with pytest.raises(picsub.PicError) as e:
+        pu.push(0, 1)                     # level 0 missing
+    assert e.value.status == 4
+    pu.fields_load(0, z, z)
+    pu.push(0, 1)
+    with pytest.raises(picsub.PicError) as e:
+        pu.push(1, 2)                     # S + order > ring depth
+    assert e.value.status == 4
+    pu.close()
+
+
+@pytest.mark.parametrize("seed", [20, 21, 22])
+def test_large_case_sampled(torch_gpu, runner, seed):
+    """2^20 electrons, a0 in {30, 100, 150}, 8192 cells, the full 100 periods
+    in the bench's launch shape; 2048 sampled particles against the oracle."""
+    torch = torch_gpu
+    wl = W.large_case(seed=seed)
+    steps = wl.steps
+    S = int(os.environ.get("PICSUB_BENCH_S", "250"))
+    _say(f"large case seed={seed} a0={wl.a0} steps={steps} S={S}")
+    run = runner.DeviceRun(wl, S=S)
+    run.reset()
+    # positions are i.i.d., so a window of caller indices is a random sample
+    first = int(np.random.default_rng(seed).integers(0, wl.num - 2048))
+    idx = np.arange(first, first + 2048)
+    buf = torch.full((steps, 2048), -2, dtype=torch.int8, device="cuda")
+    run.pusher.ktrace_set(buf, 0, first)
+    run.advance(steps)
+    d = run.diag()
+    kt = buf.cpu().numpy()
+    run.close()
+    full = np.full((steps, wl.num), -3, dtype=np.int8)
+    full[:, idx] = kt
+    from parity import compare
+    res = compare(wl, steps, d, idx, TOL64, g_ktrace=full)
+    _say({k: v for k, v in res.items() if k != "oracle_counters"})
+    g = d["counters"]
+    assert g["steps"] == steps * wl.num and g["lost"] == 0
+    assert g["sub_steps"] == sum(c << (2 * k) for k, c in enumerate(g["steps_by_k"]))
