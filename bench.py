@@ -75,8 +75,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--seed", type=int, default=22, choices=(20, 21, 22))
-    ap.add_argument("--S", type=int, default=int(os.environ.get("PICSUB_BENCH_S", "250")),
-                    help="steps of dt per push launch")
+    ap.add_argument("--S", type=int, default=int(os.environ.get("PICSUB_BENCH_S", "0")),
+                    help="steps of dt per push launch (0: the whole run in one launch)")
     ap.add_argument("--precision", default="fp64", choices=("fp64", "fp32c"))
     ap.add_argument("--binning", default="none", choices=("none", "ballot", "learned"))
     ap.add_argument("--num", type=int, default=1 << 20)
@@ -94,6 +94,8 @@ def main():
     from paper_2102_10983_amd import runner, workloads as W
 
     wl = W.large_case(seed=args.seed, num=args.num, periods=args.periods)
+    if args.S <= 0:
+        args.S = wl.steps
     run = runner.DeviceRun(wl, S=args.S, precision=args.precision, binning=args.binning)
     stream = torch.cuda.current_stream()
 
@@ -160,7 +162,8 @@ def main():
                    "n_star": counters["n_star"], "steps_by_k": counters["steps_by_k"][:9]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
-                     "kernel": "push_fp64_kernel<3>", "launches": launches,
+                     "kernel": ("push_wave_kernel<3>" if args.binning == "none"
+                                else "push_tile_kernel<3>"), "launches": launches,
                      "avg_launch_ms": avg_launch_s * 1e3,
                      "flops_per_launch": flops_step * args.steps / launches},
     }

@@ -124,7 +124,8 @@ pic_status pic_destroy(pic_ctx *ctx);
 const char *pic_last_error(const pic_ctx *ctx);
 
 /* Load the particle state: x, px, py, pz (np doubles each, the time
- * convention above) and k_old (np int8; NULL means -1 for all).  Resets
+ * convention above; may be NULL when np == 0) and k_old (np int8; NULL
+ * means -1 for all).  Resets
  * the status flags and the counters.  Particles are reordered internally
  * by position (cell index); every per-particle output is returned in the
  * caller's original order. */

@@ -25,6 +25,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -110,15 +112,21 @@ __global__ void lattice_kernel(double *__restrict__ ringE, double *__restrict__ 
 // ---------------------------------------------------------------------
 // Particle load: scatter the caller's arrays into slot order.
 // ---------------------------------------------------------------------
+// Bucket = position in units of dx / SORT_SUB: particles with nearly the
+// same position (for a cold beam, nearly the same phase history and hence
+// the same sub-cycling history) end up in neighbouring lanes.
+constexpr int SORT_SUB = 64;
+
 __global__ void cell_key_kernel(const double *__restrict__ x, int64_t np, double x_origin,
                                 double dx, int ncells, int32_t *__restrict__ key,
                                 int32_t *__restrict__ hist)
 {
+    const int32_t nfine = ncells * SORT_SUB;
     for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < np;
          i += int64_t(gridDim.x) * blockDim.x) {
-        const double u = (x[i] - x_origin) / dx;
-        int32_t c = ncells;   // bucket for anything outside the grid or NaN
-        if (u >= 0.0 && u < double(ncells)) c = int32_t(u);
+        const double u = (x[i] - x_origin) / dx * double(SORT_SUB);
+        int32_t c = nfine;   // bucket for anything outside the grid or NaN
+        if (u >= 0.0 && u < double(nfine)) c = int32_t(u);
         key[i] = c;
         atomicAdd(&hist[c], 1);
     }
@@ -392,6 +400,643 @@ __global__ void __launch_bounds__(256) push_fp64_kernel(PushArgs a)
         a.cnt[int64_t(blockIdx.x) * NCNT + c] += red[c];
 }
 
+// ---------------------------------------------------------------------
+// Tiled push with per-step compaction by k (PIC_BIN_BALLOT).
+//
+// A workgroup of TILE threads owns TILE consecutive particle slots (one
+// per thread) for all S steps of a launch.  Per step:
+//   1. the node window [lo, hi] its particles can touch during the step
+//      (a particle moves less than one cell per dt) is reduced over the
+//      workgroup and the P+1 levels of E and B on it are staged in LDS,
+//      together with B interpolated to s = 1/2 (the decision's field and
+//      the field of every k = 0 step);
+//   2. every thread takes the decision for its particle; k = 0 particles
+//      do their single sub-step in place;
+//   3. sub-cycled particles leave their state in LDS and are appended to a
+//      per-k queue with a ballot and a lane rank (mbcnt), so that each
+//      queue is a dense list; full 64-lane chunks of one k are then run by
+//      the workgroup's wavefronts, heaviest k first, with wave-uniform
+//      weights;
+//   4. owners pick their updated state back up.
+// Every particle sees exactly the arithmetic of the one-lane-per-particle
+// kernel; only which lane does it changes.
+// ---------------------------------------------------------------------
+constexpr int TILE = 256;
+constexpr int WMAX = 256;        // staged nodes per field level
+
+struct TileArgs {
+    double *x, *px, *py, *pz;
+    int8_t *kold;
+    uint8_t *status;
+    const int32_t *perm;
+    const double *ringE, *ringB;
+    const double *wtab;
+    int8_t *ktrace;
+    uint64_t *cnt;
+    int64_t np;
+    int64_t n0;
+    int64_t kt_n0, kt_first, kt_count;
+    double x_origin, dx, dt, qm, psi_max;
+    int32_t D, ncells, kmax, S, kt_steps;
+    int32_t slot0;               // ring slot of level n0 - P
+    int32_t margin;              // cells a particle can cross in one dt, + 2
+};
+
+template <int P>
+struct Levels {
+    // element offsets of the P+1 levels needed at one step, in the ring
+    int32_t off[P + 1];
+    __device__ __forceinline__ void at(const TileArgs &a, int st)
+    {
+#pragma unroll
+        for (int j = 0; j <= P; ++j) {
+            int s = a.slot0 + st + j;
+            s = s >= a.D ? s - a.D : s;
+            s = s >= a.D ? s - a.D : s;
+            off[j] = s * a.ncells;
+        }
+    }
+};
+
+// node value sum_j L_j F_j[i] from a view with level stride `ls`
+template <int P, typename T>
+__device__ __forceinline__ double node_comb(const T *__restrict__ f, const int32_t (&lo)[P + 1],
+                                            int i, const double *__restrict__ L)
+{
+    double v = L[0] * f[lo[0] + i];
+#pragma unroll
+    for (int j = 1; j <= P; ++j) v = v + L[j] * f[lo[j] + i];
+    return v;
+}
+
+struct Counts {
+    uint32_t steps[PIC_K_MAX_LIMIT + 1];
+    uint32_t clamps, lost;
+    __device__ __forceinline__ void zero()
+    {
+#pragma unroll
+        for (int k = 0; k <= PIC_K_MAX_LIMIT; ++k) steps[k] = 0;
+        clamps = lost = 0;
+    }
+    __device__ __forceinline__ void step_done(int k)
+    {
+#pragma unroll
+        for (int kk = 0; kk <= PIC_K_MAX_LIMIT; ++kk) steps[kk] += (k == kk);
+    }
+};
+
+__device__ __forceinline__ void flush_counts(Counts &c, uint64_t *__restrict__ slot)
+{
+    __shared__ uint32_t red[NCNT];
+    for (int i = threadIdx.x; i < NCNT; i += blockDim.x) red[i] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k <= PIC_K_MAX_LIMIT; ++k)
+        if (c.steps[k]) atomicAdd(&red[k], c.steps[k]);
+    if (c.clamps) atomicAdd(&red[CNT_CLAMPS], c.clamps);
+    if (c.lost) atomicAdd(&red[CNT_LOST], c.lost);
+    __syncthreads();
+    for (int i = threadIdx.x; i < NCNT; i += blockDim.x) slot[i] += red[i];
+}
+
+__device__ __forceinline__ int wave_min(int v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = min(v, __shfl_xor(v, o));
+    return v;
+}
+
+__device__ __forceinline__ int wave_max(int v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o));
+    return v;
+}
+
+template <int P>
+__global__ void __launch_bounds__(TILE) push_tile_kernel(TileArgs a)
+{
+    constexpr int STRIDE = 2 * (P + 1);
+    __shared__ double sE[(P + 1) * WMAX];    // raw E levels on the window
+    __shared__ double sB[(P + 1) * WMAX];    // raw B levels on the window
+    __shared__ double sBh[WMAX];             // B at s = 1/2 on the window
+    __shared__ double sx[TILE], spx[TILE], spy[TILE], spz[TILE];
+    __shared__ uint8_t sst[TILE];
+    __shared__ uint16_t sq[PIC_K_MAX_LIMIT + 1][TILE];
+    __shared__ int sqn[PIC_K_MAX_LIMIT + 1];
+    __shared__ int slo[2], shi[2];   // window bounds, double-buffered by step parity
+
+    const int t = threadIdx.x;
+    const int lane = t & 63;
+    const int wave = t >> 6;
+    constexpr int NWAVE = TILE / 64;
+    const double ncm1 = double(a.ncells - 1);
+    const double c0 = 0.5 * a.qm * a.dt;
+    const double *W1 = a.wtab;                 // (k = 0, j = 1): s = 1/2
+    Counts cnt;
+    cnt.zero();
+
+    if (t <= PIC_K_MAX_LIMIT) sqn[t] = 0;
+    if (t < 2) {
+        slo[t] = INT_MAX;
+        shi[t] = INT_MIN;
+    }
+
+    for (int64_t tile0 = int64_t(blockIdx.x) * TILE; tile0 < a.np;
+         tile0 += int64_t(gridDim.x) * TILE) {
+        const int64_t i = tile0 + t;
+        const bool mine = i < a.np;
+        double x = 0, px = 0, py = 0, pz = 0;
+        int kold = 0;
+        uint8_t status = PIC_PARTICLE_LOST;
+        int64_t kt_u = -1;
+        if (mine) {
+            x = a.x[i];
+            px = a.px[i];
+            py = a.py[i];
+            pz = a.pz[i];
+            kold = a.kold[i];
+            status = a.status[i];
+            if (a.ktrace) {
+                const int64_t u = a.perm[i] - a.kt_first;
+                if (u >= 0 && u < a.kt_count) kt_u = u;
+            }
+        }
+        __syncthreads();     // previous tile's LDS use is over
+
+        for (int st = 0; st < a.S; ++st) {
+            Levels<P> lv;
+            lv.at(a, st);
+            // -- 1. window of nodes this tile may touch during the step
+            double xi = (x - a.x_origin) / a.dx;
+            bool live = status == PIC_PARTICLE_LIVE && xi >= 0.5 && xi < ncm1;
+            if (status == PIC_PARTICLE_LIVE && !live) {
+                status = PIC_PARTICLE_LOST;
+                ++cnt.lost;
+                if (kt_u >= 0) {
+                    const int64_t r = a.n0 + st - a.kt_n0;
+                    if (r >= 0 && r < a.kt_steps) a.ktrace[r * a.kt_count + kt_u] = -1;
+                }
+            } else if (!live && kt_u >= 0) {
+                const int64_t r = a.n0 + st - a.kt_n0;
+                if (r >= 0 && r < a.kt_steps) a.ktrace[r * a.kt_count + kt_u] = -1;
+            }
+            const int par = st & 1;
+            const int cell = live ? int(floor(xi)) : 0;
+            int wlo = wave_min(live ? cell - a.margin : INT_MAX);
+            int whi = wave_max(live ? cell + a.margin : INT_MIN);
+            if (lane == 0 && wlo <= whi) {
+                atomicMin(&slo[par], wlo);
+                atomicMax(&shi[par], whi);
+            }
+            __syncthreads();
+            const int lo = max(slo[par], 0);
+            const int hi = min(shi[par], a.ncells - 1);
+            const bool any = slo[par] <= shi[par];
+            const bool use_lds = any && hi - lo + 1 <= WMAX;
+            // -- stage the window
+            if (use_lds) {
+                for (int q = t; q <= hi - lo; q += TILE) {
+                    double bh = 0;
+#pragma unroll
+                    for (int j = 0; j <= P; ++j) {
+                        const double e = a.ringE[lv.off[j] + lo + q];
+                        const double b = a.ringB[lv.off[j] + lo + q];
+                        sE[j * WMAX + q] = e;
+                        sB[j * WMAX + q] = b;
+                        bh = j == 0 ? W1[P + 1] * b : bh + W1[P + 1 + j] * b;
+                    }
+                    sBh[q] = bh;
+                }
+            }
+            __syncthreads();
+            // this parity's bounds are read by everyone; the next writes to
+            // them come two steps on, after the next step's first barrier
+            if (t == 0) {
+                slo[par] = INT_MAX;
+                shi[par] = INT_MIN;
+            }
+            if (!any) continue;     // uniform: nothing live in this tile
+
+            int32_t vo[P + 1];       // LDS level offsets shifted by the window base
+#pragma unroll
+            for (int j = 0; j <= P; ++j) vo[j] = j * WMAX - lo;
+
+            // -- 2. decision, k = 0 steps in place
+            bool heavy = false;
+            int k = 0;
+            if (live) {
+                const double flB = floor(xi);
+                const int iB = int(flB);
+                const double wB = xi - flB;
+                double f0, f1;
+                if (use_lds) {
+                    f0 = sBh[iB - lo];
+                    f1 = sBh[iB + 1 - lo];
+                } else {
+                    f0 = node_comb<P>(a.ringB, lv.off, iB, W1 + P + 1);
+                    f1 = node_comb<P>(a.ringB, lv.off, iB + 1, W1 + P + 1);
+                }
+                const double Bd = (1.0 - wB) * f0 + wB * f1;
+                const double g0 = sqrt(1.0 + ((px * px + py * py) + pz * pz));
+                const double psi0 = fabs(c0 * Bd) / g0;
+                double lim = a.psi_max;
+                while (psi0 > lim && k < a.kmax) {
+                    ++k;
+                    lim = lim * 4.0;
+                }
+                cnt.clamps += psi0 > lim;
+                if (kt_u >= 0) {
+                    const int64_t r = a.n0 + st - a.kt_n0;
+                    if (r >= 0 && r < a.kt_steps) a.ktrace[r * a.kt_count + kt_u] = int8_t(k);
+                }
+                const int ko = kold < 0 ? k : kold;
+                kold = k;
+                if (k == 0) {
+                    const double uE = xi - 0.5;
+                    const double flE = floor(uE);
+                    const int iE = int(flE);
+                    const double wE = uE - flE;
+                    // s = 1/2 is the time of level n: E's weights are
+                    // (0, .., 0, 1), so the node values are level n's
+                    double e0, e1;
+                    if (use_lds) {
+                        e0 = sE[vo[P] + iE];
+                        e1 = sE[vo[P] + iE + 1];
+                    } else {
+                        e0 = a.ringE[lv.off[P] + iE];
+                        e1 = a.ringE[lv.off[P] + iE + 1];
+                    }
+                    const double E = (1.0 - wE) * e0 + wE * e1;
+                    const double dto = ldexp(a.dt, -2 * ko);
+                    boris(a.qm, 0.5 * (dto + a.dt), E, Bd, px, py, pz);
+                    const double g2 = sqrt(1.0 + ((px * px + py * py) + pz * pz));
+                    x = x + a.dt * (px / g2);
+                    cnt.step_done(0);
+                } else {
+                    heavy = true;
+                    // remember dt*_old through the LDS state: pack it in kold
+                    sx[t] = x;
+                    spx[t] = px;
+                    spy[t] = py;
+                    spz[t] = pz;
+                    sst[t] = uint8_t(ko);
+                }
+            }
+            // -- 3. per-k queues: ballot + lane rank
+            if (__syncthreads_or(heavy)) {
+                for (int kk = 1; kk <= a.kmax; ++kk) {
+                    const uint64_t m = __ballot(heavy && k == kk);
+                    if (m) {
+                        int base = 0;
+                        if (lane == 0) base = atomicAdd(&sqn[kk], __popcll(m));
+                        base = __shfl(base, 0);
+                        if (heavy && k == kk) {
+                            const uint32_t below =
+                                __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32),
+                                                          __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u));
+                            sq[kk][base + below] = uint16_t(t);
+                        }
+                    }
+                }
+                __syncthreads();
+                // chunks ordered by k descending; wave w takes every NWAVE-th
+                int total = 0;
+                for (int kk = a.kmax; kk >= 1; --kk) total += (sqn[kk] + 63) >> 6;
+                for (int g = wave; g < total; g += NWAVE) {
+                    int kk = a.kmax, c = g;
+                    while (c >= ((sqn[kk] + 63) >> 6)) {
+                        c -= (sqn[kk] + 63) >> 6;
+                        --kk;
+                    }
+                    kk = __builtin_amdgcn_readfirstlane(kk);
+                    const int e = c * 64 + lane;
+                    if (e >= sqn[kk]) continue;
+                    const int who = sq[kk][e];
+                    double hx = sx[who], hpx = spx[who], hpy = spy[who], hpz = spz[who];
+                    const int ko = sst[who];
+                    const double dt_new = ldexp(a.dt, -2 * kk);
+                    const double dt_old = ldexp(a.dt, -2 * ko);
+                    const int nsub = 1 << (2 * kk);
+                    const double *Wk = a.wtab + wtab_offset(kk) * STRIDE;
+                    uint8_t hst = PIC_PARTICLE_LIVE;
+                    for (int j = 1; j <= nsub; ++j, Wk += STRIDE) {
+                        const double hxi = (hx - a.x_origin) / a.dx;
+                        if (!(hxi >= 0.5 && hxi < ncm1)) {
+                            hst = PIC_PARTICLE_LOST;
+                            break;
+                        }
+                        const double flB = floor(hxi);
+                        const int iB = int(flB);
+                        const double wB = hxi - flB;
+                        const double uE = hxi - 0.5;
+                        const double flE = floor(uE);
+                        const int iE = int(flE);
+                        const double wE = uE - flE;
+                        double b0, b1, e0, e1;
+                        if (use_lds) {
+                            b0 = node_comb<P>(sB, vo, iB, Wk + P + 1);
+                            b1 = node_comb<P>(sB, vo, iB + 1, Wk + P + 1);
+                            e0 = node_comb<P>(sE, vo, iE, Wk);
+                            e1 = node_comb<P>(sE, vo, iE + 1, Wk);
+                        } else {
+                            b0 = node_comb<P>(a.ringB, lv.off, iB, Wk + P + 1);
+                            b1 = node_comb<P>(a.ringB, lv.off, iB + 1, Wk + P + 1);
+                            e0 = node_comb<P>(a.ringE, lv.off, iE, Wk);
+                            e1 = node_comb<P>(a.ringE, lv.off, iE + 1, Wk);
+                        }
+                        const double B = (1.0 - wB) * b0 + wB * b1;
+                        const double E = (1.0 - wE) * e0 + wE * e1;
+                        const double dtp = j == 1 ? 0.5 * (dt_old + dt_new) : dt_new;
+                        boris(a.qm, dtp, E, B, hpx, hpy, hpz);
+                        const double g2 = sqrt(1.0 + ((hpx * hpx + hpy * hpy) + hpz * hpz));
+                        hx = hx + dt_new * (hpx / g2);
+                    }
+                    sx[who] = hx;
+                    spx[who] = hpx;
+                    spy[who] = hpy;
+                    spz[who] = hpz;
+                    sst[who] = hst == PIC_PARTICLE_LIVE ? uint8_t(0xFF) : hst;
+                }
+                __syncthreads();
+                if (heavy) {
+                    x = sx[t];
+                    px = spx[t];
+                    py = spy[t];
+                    pz = spz[t];
+                    if (sst[t] == 0xFF) {
+                        cnt.step_done(k);
+                    } else {
+                        status = PIC_PARTICLE_LOST;
+                        ++cnt.lost;
+                    }
+                }
+                if (t <= PIC_K_MAX_LIMIT) sqn[t] = 0;
+                // the next step's first barrier orders these resets before
+                // any new enqueue
+            }
+        }
+        if (mine) {
+            a.x[i] = x;
+            a.px[i] = px;
+            a.py[i] = py;
+            a.pz[i] = pz;
+            a.kold[i] = int8_t(kold);
+            a.status[i] = status;
+        }
+    }
+    flush_counts(cnt, a.cnt + int64_t(blockIdx.x) * NCNT);
+}
+
+// ---------------------------------------------------------------------
+// Asynchronous wavefront push.
+//
+// One wavefront per workgroup and one workgroup per group of 64
+// consecutive particle slots, carried through all S steps of the launch;
+// the dispatcher starts a new workgroup wherever one retires, so no
+// particle ever waits for another wavefront: a particle that sub-cycles
+// deeply holds up only its own group while every other wavefront keeps
+// advancing (the steps' field levels are all resident in the ring).
+// Slots are sorted by position at load, so the 64 lanes of a group hold
+// electrons with nearly the same phase history and mostly choose the same
+// k.  Per step the group's node window is staged in the wavefront's own
+// LDS (raw levels plus B at s = 1/2).  The arithmetic of every particle
+// is that of the other push kernels.
+// ---------------------------------------------------------------------
+
+__device__ __forceinline__ void flush_counts_atomic(Counts &c, uint64_t *__restrict__ slot)
+{
+    __shared__ uint32_t red[NCNT];
+    for (int i = threadIdx.x; i < NCNT; i += blockDim.x) red[i] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k <= PIC_K_MAX_LIMIT; ++k)
+        if (c.steps[k]) atomicAdd(&red[k], c.steps[k]);
+    if (c.clamps) atomicAdd(&red[CNT_CLAMPS], c.clamps);
+    if (c.lost) atomicAdd(&red[CNT_LOST], c.lost);
+    __syncthreads();
+    for (int i = threadIdx.x; i < NCNT; i += blockDim.x)
+        if (red[i]) atomicAdd(reinterpret_cast<unsigned long long *>(slot + i),
+                              static_cast<unsigned long long>(red[i]));
+}
+
+constexpr int WWIN = 64;         // staged nodes per level in a wavefront window
+
+struct WaveArgs {
+    double *x, *px, *py, *pz;
+    int8_t *kold;
+    uint8_t *status;
+    const int32_t *perm;
+    const double *ringE, *ringB;
+    const double *wtab;
+    int8_t *ktrace;
+    uint64_t *cnt;               // nslot counter slots, shared through atomics
+    int32_t nslot;
+    int64_t np;
+    int64_t n0;
+    int64_t kt_n0, kt_first, kt_count;
+    double x_origin, dx, dt, qm, psi_max;
+    int32_t D, ncells, kmax, S, kt_steps;
+    int32_t slot0;
+    int32_t margin;
+};
+
+template <int P>
+struct WaveLevels {
+    int32_t off[P + 1];
+    __device__ __forceinline__ void at(const WaveArgs &a, int st)
+    {
+#pragma unroll
+        for (int j = 0; j <= P; ++j) {
+            int s = a.slot0 + st + j;
+            s = s >= a.D ? s - a.D : s;
+            s = s >= a.D ? s - a.D : s;
+            off[j] = s * a.ncells;
+        }
+    }
+};
+
+template <int P>
+__global__ void __launch_bounds__(64) push_wave_kernel(WaveArgs a)
+{
+    constexpr int STRIDE = 2 * (P + 1);
+    __shared__ double sE[(P + 1) * WWIN];
+    __shared__ double sB[(P + 1) * WWIN];
+    __shared__ double sBh[WWIN];
+    const int lane = threadIdx.x;
+    const double ncm1 = double(a.ncells - 1);
+    const double c0 = 0.5 * a.qm * a.dt;
+    const double *W1 = a.wtab;
+    Counts cnt;
+    cnt.zero();
+    {
+        const int64_t i = int64_t(blockIdx.x) * 64 + lane;
+        const bool mine = i < a.np;
+        double x = 0, px = 0, py = 0, pz = 0;
+        int kold = 0;
+        uint8_t status = PIC_PARTICLE_LOST;
+        int64_t kt_u = -1;
+        if (mine) {
+            x = a.x[i];
+            px = a.px[i];
+            py = a.py[i];
+            pz = a.pz[i];
+            kold = a.kold[i];
+            status = a.status[i];
+            if (a.ktrace) {
+                const int64_t u = a.perm[i] - a.kt_first;
+                if (u >= 0 && u < a.kt_count) kt_u = u;
+            }
+        }
+        for (int st = 0; st < a.S; ++st) {
+            WaveLevels<P> lv;
+            lv.at(a, st);
+            double xi = (x - a.x_origin) / a.dx;
+            const bool live = status == PIC_PARTICLE_LIVE && xi >= 0.5 && xi < ncm1;
+            if (status == PIC_PARTICLE_LIVE && !live) {
+                status = PIC_PARTICLE_LOST;
+                ++cnt.lost;
+            }
+            if (!live && kt_u >= 0) {
+                const int64_t r = a.n0 + st - a.kt_n0;
+                if (r >= 0 && r < a.kt_steps) a.ktrace[r * a.kt_count + kt_u] = -1;
+            }
+            if (!__any(live)) {          // wave-uniform: the group is done
+                if (kt_u >= 0)
+                    for (int s2 = st + 1; s2 < a.S; ++s2) {
+                        const int64_t r = a.n0 + s2 - a.kt_n0;
+                        if (r >= 0 && r < a.kt_steps) a.ktrace[r * a.kt_count + kt_u] = -1;
+                    }
+                break;
+            }
+            const int cell = live ? int(floor(xi)) : 0;
+            const int lo = max(wave_min(live ? cell - a.margin : INT_MAX), 0);
+            const int hi = min(wave_max(live ? cell + a.margin : INT_MIN), a.ncells - 1);
+            const bool use_lds = hi - lo + 1 <= WWIN;
+            if (use_lds) {
+                __syncthreads();          // one wavefront: orders the previous step's reads
+                for (int q = lane; q <= hi - lo; q += 64) {
+                    double bh = 0;
+#pragma unroll
+                    for (int j = 0; j <= P; ++j) {
+                        const double e = a.ringE[lv.off[j] + lo + q];
+                        const double b = a.ringB[lv.off[j] + lo + q];
+                        sE[j * WWIN + q] = e;
+                        sB[j * WWIN + q] = b;
+                        bh = j == 0 ? W1[P + 1] * b : bh + W1[P + 1 + j] * b;
+                    }
+                    sBh[q] = bh;
+                }
+                __syncthreads();
+            }
+            int32_t vo[P + 1];
+#pragma unroll
+            for (int j = 0; j <= P; ++j) vo[j] = j * WWIN - lo;
+            if (!live) continue;
+
+            // decision: B at (x_n, s = 1/2), gamma of the stored momentum
+            const double flB = floor(xi);
+            const int iB = int(flB);
+            const double wB = xi - flB;
+            double f0, f1;
+            if (use_lds) {
+                f0 = sBh[iB - lo];
+                f1 = sBh[iB + 1 - lo];
+            } else {
+                f0 = node_comb<P>(a.ringB, lv.off, iB, W1 + P + 1);
+                f1 = node_comb<P>(a.ringB, lv.off, iB + 1, W1 + P + 1);
+            }
+            const double Bd = (1.0 - wB) * f0 + wB * f1;
+            const double g0 = sqrt(1.0 + ((px * px + py * py) + pz * pz));
+            const double psi0 = fabs(c0 * Bd) / g0;
+            int k = 0;
+            double lim = a.psi_max;
+            while (psi0 > lim && k < a.kmax) {
+                ++k;
+                lim = lim * 4.0;
+            }
+            cnt.clamps += psi0 > lim;
+            if (kt_u >= 0) {
+                const int64_t r = a.n0 + st - a.kt_n0;
+                if (r >= 0 && r < a.kt_steps) a.ktrace[r * a.kt_count + kt_u] = int8_t(k);
+            }
+            const int ko = kold < 0 ? k : kold;
+            kold = k;
+            const double dt_new = ldexp(a.dt, -2 * k);
+            const double dt_old = ldexp(a.dt, -2 * ko);
+            const int nsub = 1 << (2 * k);
+            const double *Wk = a.wtab + wtab_offset(k) * STRIDE;
+            bool done = true;
+            for (int j = 1; j <= nsub; ++j, Wk += STRIDE) {
+                double B, E;
+                if (j == 1) {
+                    // s = 1/2: B is the decision's, E's weights pick level n
+                    B = Bd;
+                    const double uE = xi - 0.5;
+                    const double flE = floor(uE);
+                    const int iE = int(flE);
+                    const double wE = uE - flE;
+                    double e0, e1;
+                    if (use_lds) {
+                        e0 = sE[vo[P] + iE];
+                        e1 = sE[vo[P] + iE + 1];
+                    } else {
+                        e0 = a.ringE[lv.off[P] + iE];
+                        e1 = a.ringE[lv.off[P] + iE + 1];
+                    }
+                    E = (1.0 - wE) * e0 + wE * e1;
+                } else {
+                    xi = (x - a.x_origin) / a.dx;
+                    if (!(xi >= 0.5 && xi < ncm1)) {
+                        done = false;
+                        break;
+                    }
+                    const double fl = floor(xi);
+                    const int ib = int(fl);
+                    const double wb = xi - fl;
+                    const double uE = xi - 0.5;
+                    const double flE = floor(uE);
+                    const int iE = int(flE);
+                    const double wE = uE - flE;
+                    double b0, b1, e0, e1;
+                    if (use_lds) {
+                        b0 = node_comb<P>(sB, vo, ib, Wk + P + 1);
+                        b1 = node_comb<P>(sB, vo, ib + 1, Wk + P + 1);
+                        e0 = node_comb<P>(sE, vo, iE, Wk);
+                        e1 = node_comb<P>(sE, vo, iE + 1, Wk);
+                    } else {
+                        b0 = node_comb<P>(a.ringB, lv.off, ib, Wk + P + 1);
+                        b1 = node_comb<P>(a.ringB, lv.off, ib + 1, Wk + P + 1);
+                        e0 = node_comb<P>(a.ringE, lv.off, iE, Wk);
+                        e1 = node_comb<P>(a.ringE, lv.off, iE + 1, Wk);
+                    }
+                    B = (1.0 - wb) * b0 + wb * b1;
+                    E = (1.0 - wE) * e0 + wE * e1;
+                }
+                const double dtp = j == 1 ? 0.5 * (dt_old + dt_new) : dt_new;
+                boris(a.qm, dtp, E, B, px, py, pz);
+                const double g2 = sqrt(1.0 + ((px * px + py * py) + pz * pz));
+                x = x + dt_new * (px / g2);
+            }
+            if (done) {
+                cnt.step_done(k);
+            } else {
+                status = PIC_PARTICLE_LOST;
+                ++cnt.lost;
+            }
+        }
+        if (mine) {
+            a.x[i] = x;
+            a.px[i] = px;
+            a.py[i] = py;
+            a.pz[i] = pz;
+            a.kold[i] = int8_t(kold);
+            a.status[i] = status;
+        }
+    }
+    flush_counts_atomic(cnt, a.cnt + int64_t(blockIdx.x % a.nslot) * NCNT);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------
@@ -402,7 +1047,9 @@ struct pic_ctx {
     int64_t np = 0;
     hipStream_t stream = nullptr;
     int device = 0;
-    int grid = 0;        // persistent workgroups of the push
+    int ncu = 0;
+    int grid = 0;        // persistent workgroups of the one-lane-per-particle push
+    int tile_grid = 0;   // workgroups of the tiled push
     int block = 256;
     int tile = 256;
     bool have_particles = false;
@@ -484,6 +1131,7 @@ pic_status check_params(pic_ctx *ctx, const pic_params *p, int64_t np)
     if (p->k_max < 0 || p->k_max > PIC_K_MAX_LIMIT)
         return fail(ctx, PIC_E_ARG, "k_max must be in [0, %d]", PIC_K_MAX_LIMIT);
     if (!(p->dx > 0) || !(p->dt > 0)) return fail(ctx, PIC_E_ARG, "dx and dt must be > 0");
+    if (!(p->dt <= 64.0 * p->dx)) return fail(ctx, PIC_E_ARG, "dt / dx must be <= 64");
     if (!(p->psi_max > 0)) return fail(ctx, PIC_E_ARG, "psi_max must be > 0");
     if (!(p->qm != 0) || p->qm != p->qm) return fail(ctx, PIC_E_ARG, "qm must be nonzero");
     if (p->x_origin != p->x_origin) return fail(ctx, PIC_E_ARG, "x_origin is NaN");
@@ -491,8 +1139,10 @@ pic_status check_params(pic_ctx *ctx, const pic_params *p, int64_t np)
         return fail(ctx, PIC_E_ARG, "unknown precision %d", p->precision);
     if (p->binning < PIC_BIN_NONE || p->binning > PIC_BIN_LEARNED)
         return fail(ctx, PIC_E_ARG, "unknown binning %d", p->binning);
-    if (int64_t(p->ring_depth) * p->ncells > (int64_t(1) << 34))
-        return fail(ctx, PIC_E_ARG, "ring too large");
+    if (int64_t(p->ring_depth) * p->ncells >= (int64_t(1) << 31))
+        return fail(ctx, PIC_E_ARG, "ring_depth * ncells must stay below 2^31");
+    if (int64_t(p->ncells) * SORT_SUB >= (int64_t(1) << 30))
+        return fail(ctx, PIC_E_ARG, "ncells too large");
     return PIC_OK;
 }
 
@@ -538,14 +1188,16 @@ pic_status pic_create(const pic_params *prm, int64_t np, void *hip_stream, pic_c
     const size_t n = size_t(np);
     const size_t ring = size_t(prm->ring_depth) * prm->ncells;
     const int64_t went = wtab_entries(prm->k_max);
+    ctx->ncu = ncu;
     ctx->grid = grid_for(np, ctx->block, ncu * 8);
+    ctx->tile_grid = grid_for(np, TILE, ncu * 16);
     if ((st = dev_alloc(ctx, &ctx->x, n)) || (st = dev_alloc(ctx, &ctx->px, n)) ||
         (st = dev_alloc(ctx, &ctx->py, n)) || (st = dev_alloc(ctx, &ctx->pz, n)) ||
         (st = dev_alloc(ctx, &ctx->kold, n)) || (st = dev_alloc(ctx, &ctx->status, n)) ||
         (st = dev_alloc(ctx, &ctx->perm, n)) || (st = dev_alloc(ctx, &ctx->key, n)) ||
         (st = dev_alloc(ctx, &ctx->ringE, ring)) || (st = dev_alloc(ctx, &ctx->ringB, ring)) ||
         (st = dev_alloc(ctx, &ctx->wtab, size_t(went) * 2 * (prm->order + 1))) ||
-        (st = dev_alloc(ctx, &ctx->cnt, size_t(ncu) * 8 * NCNT))) {
+        (st = dev_alloc(ctx, &ctx->cnt, size_t(ncu) * 16 * NCNT))) {
         free_all(ctx);
         ctx->x = ctx->px = ctx->py = ctx->pz = ctx->ringE = ctx->ringB = ctx->wtab = nullptr;
         ctx->kold = nullptr;
@@ -560,7 +1212,7 @@ pic_status pic_create(const pic_params *prm, int64_t np, void *hip_stream, pic_c
     weights_kernel<<<grid_for(went, 256, 4096), 256, 0, ctx->stream>>>(ctx->wtab, prm->order,
                                                                         prm->k_max);
     LAUNCH_CHECK(ctx);
-    HIP_TRY(ctx, hipMemsetAsync(ctx->cnt, 0, size_t(ncu) * 8 * NCNT * sizeof(uint64_t),
+    HIP_TRY(ctx, hipMemsetAsync(ctx->cnt, 0, size_t(ncu) * 16 * NCNT * sizeof(uint64_t),
                                 ctx->stream));
     HIP_TRY(ctx, hipMemsetAsync(ctx->status, PIC_PARTICLE_LOST, n ? n : 1, ctx->stream));
     return PIC_OK;
@@ -584,9 +1236,9 @@ pic_status pic_particles_set(pic_ctx *ctx, pic_mem mem, const double *x, const d
                              const double *py, const double *pz, const int8_t *k_old)
 {
     if (!ctx || !ctx->x) return ctx ? fail(ctx, PIC_E_STATE, "context not created") : PIC_E_ARG;
-    if (!x || !px || !py || !pz) return fail(ctx, PIC_E_ARG, "null particle array");
-    if (mem != PIC_MEM_HOST && mem != PIC_MEM_DEVICE) return fail(ctx, PIC_E_ARG, "bad pic_mem");
     const int64_t np = ctx->np;
+    if (np > 0 && (!x || !px || !py || !pz)) return fail(ctx, PIC_E_ARG, "null particle array");
+    if (mem != PIC_MEM_HOST && mem != PIC_MEM_DEVICE) return fail(ctx, PIC_E_ARG, "bad pic_mem");
     const size_t n = size_t(np);
     const double *dx_ = x, *dpx = px, *dpy = py, *dpz = pz;
     const int8_t *dk = k_old;
@@ -618,7 +1270,7 @@ pic_status pic_particles_set(pic_ctx *ctx, pic_mem mem, const double *x, const d
     }
     pic_status result = PIC_OK;
     if (np > 0) {
-        const int nb = ctx->prm.ncells + 1;
+        const int nb = ctx->prm.ncells * SORT_SUB + 1;
         int32_t *hist = nullptr;
         if ((result = dev_alloc(ctx, &hist, size_t(nb)))) goto done;
         if (hipMemsetAsync(hist, 0, size_t(nb) * sizeof(int32_t), ctx->stream) != hipSuccess) {
@@ -650,7 +1302,7 @@ pic_status pic_particles_set(pic_ctx *ctx, pic_mem mem, const double *x, const d
         }
     }
     {
-        hipError_t e = hipMemsetAsync(ctx->cnt, 0, size_t(ctx->grid) * NCNT * sizeof(uint64_t),
+        hipError_t e = hipMemsetAsync(ctx->cnt, 0, size_t(ctx->ncu) * 16 * NCNT * sizeof(uint64_t),
                                       ctx->stream);
         if (e != hipSuccess) result = fail(ctx, PIC_E_DEVICE, "hipMemsetAsync: %s", hipGetErrorString(e));
     }
@@ -754,11 +1406,85 @@ pic_status pic_push_subcycled(pic_ctx *ctx, int64_t n, int32_t S)
     a.ncells = p.ncells;
     a.kmax = p.k_max;
     a.S = S;
-    const dim3 grid(ctx->grid), block(256);
+    const int32_t slot0 = int32_t(mod_floor(n - p.order, p.ring_depth));
+    // |v| < c, so a particle crosses fewer than dt / dx cells per step
+    const int32_t margin = int32_t(std::ceil(p.dt / p.dx)) + 2;
+    if (p.binning == PIC_BIN_NONE) {
+        WaveArgs wa;
+        wa.x = ctx->x;
+        wa.px = ctx->px;
+        wa.py = ctx->py;
+        wa.pz = ctx->pz;
+        wa.kold = ctx->kold;
+        wa.status = ctx->status;
+        wa.perm = ctx->perm;
+        wa.ringE = ctx->ringE;
+        wa.ringB = ctx->ringB;
+        wa.wtab = ctx->wtab;
+        wa.ktrace = ctx->ktrace;
+        wa.cnt = ctx->cnt;
+        wa.nslot = ctx->ncu * 16;
+        wa.np = ctx->np;
+        wa.n0 = n;
+        wa.kt_n0 = ctx->kt_n0;
+        wa.kt_first = ctx->kt_first;
+        wa.kt_count = ctx->kt_count;
+        wa.x_origin = p.x_origin;
+        wa.dx = p.dx;
+        wa.dt = p.dt;
+        wa.qm = p.qm;
+        wa.psi_max = p.psi_max;
+        wa.D = p.ring_depth;
+        wa.ncells = p.ncells;
+        wa.kmax = p.k_max;
+        wa.S = S;
+        wa.kt_steps = ctx->kt_steps;
+        wa.slot0 = slot0;
+        wa.margin = margin;
+        const dim3 grid(unsigned((ctx->np + 63) / 64)), block(64);
+        switch (p.order) {
+        case 1: push_wave_kernel<1><<<grid, block, 0, ctx->stream>>>(wa); break;
+        case 3: push_wave_kernel<3><<<grid, block, 0, ctx->stream>>>(wa); break;
+        default: push_wave_kernel<5><<<grid, block, 0, ctx->stream>>>(wa); break;
+        }
+        LAUNCH_CHECK(ctx);
+        return PIC_OK;
+    }
+    TileArgs ta;
+    ta.x = ctx->x;
+    ta.px = ctx->px;
+    ta.py = ctx->py;
+    ta.pz = ctx->pz;
+    ta.kold = ctx->kold;
+    ta.status = ctx->status;
+    ta.perm = ctx->perm;
+    ta.ringE = ctx->ringE;
+    ta.ringB = ctx->ringB;
+    ta.wtab = ctx->wtab;
+    ta.ktrace = ctx->ktrace;
+    ta.cnt = ctx->cnt;
+    ta.np = ctx->np;
+    ta.n0 = n;
+    ta.kt_n0 = ctx->kt_n0;
+    ta.kt_first = ctx->kt_first;
+    ta.kt_count = ctx->kt_count;
+    ta.x_origin = p.x_origin;
+    ta.dx = p.dx;
+    ta.dt = p.dt;
+    ta.qm = p.qm;
+    ta.psi_max = p.psi_max;
+    ta.D = p.ring_depth;
+    ta.ncells = p.ncells;
+    ta.kmax = p.k_max;
+    ta.S = S;
+    ta.kt_steps = ctx->kt_steps;
+    ta.slot0 = slot0;
+    ta.margin = margin;
+    const dim3 tgrid(ctx->tile_grid), tblock(TILE);
     switch (p.order) {
-    case 1: push_fp64_kernel<1><<<grid, block, 0, ctx->stream>>>(a); break;
-    case 3: push_fp64_kernel<3><<<grid, block, 0, ctx->stream>>>(a); break;
-    default: push_fp64_kernel<5><<<grid, block, 0, ctx->stream>>>(a); break;
+    case 1: push_tile_kernel<1><<<tgrid, tblock, 0, ctx->stream>>>(ta); break;
+    case 3: push_tile_kernel<3><<<tgrid, tblock, 0, ctx->stream>>>(ta); break;
+    default: push_tile_kernel<5><<<tgrid, tblock, 0, ctx->stream>>>(ta); break;
     }
     LAUNCH_CHECK(ctx);
     return PIC_OK;
@@ -767,7 +1493,7 @@ pic_status pic_push_subcycled(pic_ctx *ctx, int64_t n, int32_t S)
 pic_status pic_counters_reset(pic_ctx *ctx)
 {
     if (!ctx || !ctx->x) return ctx ? fail(ctx, PIC_E_STATE, "context not created") : PIC_E_ARG;
-    HIP_TRY(ctx, hipMemsetAsync(ctx->cnt, 0, size_t(ctx->grid) * NCNT * sizeof(uint64_t),
+    HIP_TRY(ctx, hipMemsetAsync(ctx->cnt, 0, size_t(ctx->ncu) * 16 * NCNT * sizeof(uint64_t),
                                 ctx->stream));
     return PIC_OK;
 }
@@ -821,13 +1547,13 @@ pic_status pic_diag(pic_ctx *ctx, pic_mem mem, double *gamma, double *px, double
         }
     }
     if (cnt) {
-        std::vector<uint64_t> h(size_t(ctx->grid) * NCNT);
+        std::vector<uint64_t> h(size_t(ctx->ncu) * 16 * NCNT);
         HIP_TRY(ctx, hipMemcpyAsync(h.data(), ctx->cnt, h.size() * sizeof(uint64_t),
                                     hipMemcpyDeviceToHost, ctx->stream));
         HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
         std::memset(cnt, 0, sizeof *cnt);
-        for (int b = 0; b < ctx->grid; ++b) {
-            const uint64_t *r = h.data() + size_t(b) * NCNT;
+        for (size_t b = 0; b < h.size() / NCNT; ++b) {
+            const uint64_t *r = h.data() + b * NCNT;
             for (int k = 0; k < PIC_KHIST; ++k) cnt->steps_by_k[k] += r[k];
             cnt->clamps += r[CNT_CLAMPS];
             cnt->lost += r[CNT_LOST];

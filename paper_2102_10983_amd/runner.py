@@ -13,7 +13,7 @@ class DeviceRun:
     """A Pusher bound to one workload, with its phase table on the device."""
 
     def __init__(self, wl: W.Workload, *, S: int = 1, order: int | None = None,
-                 psi_max: float | None = None, precision: str = "fp64", binning: str = "none",
+                 psi_max: float | None = None, precision: str = "fp64", binning: str = "ballot",
                  k_max: int = 8, ring_extra: int = 0, stream=None):
         import torch
         self.torch = torch

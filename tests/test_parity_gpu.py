@@ -43,8 +43,9 @@ def _ktrace(torch, run, steps):
     return buf
 
 
-def _gpu_full(torch, runner, wl, steps, S, order=None, psi_max=None, trace=True):
-    run = runner.DeviceRun(wl, S=S, order=order, psi_max=psi_max)
+def _gpu_full(torch, runner, wl, steps, S, order=None, psi_max=None, trace=True,
+              binning="ballot"):
+    run = runner.DeviceRun(wl, S=S, order=order, psi_max=psi_max, binning=binning)
     run.reset()
     buf = _ktrace(torch, run, steps) if trace else None
     run.advance(steps)
@@ -73,12 +74,14 @@ def test_single_step(torch_gpu, runner, order):
     assert res["flips"] == 0
 
 
-@pytest.mark.parametrize("order,S", [(1, 1), (3, 1), (3, 16), (1, 75)])
-def test_small_case_full_run(torch_gpu, runner, order, S):
+@pytest.mark.parametrize("order,S,binning", [(1, 1, "none"), (3, 1, "none"), (3, 16, "none"),
+                                             (1, 75, "ballot"), (3, 1, "ballot"),
+                                             (3, 250, "ballot")])
+def test_small_case_full_run(torch_gpu, runner, order, S, binning):
     """1024 electrons, a0 = 10, T/dt = 75, 2048 cells, 20 periods."""
-    _say(f"small case order={order} S={S}")
+    _say(f"small case order={order} S={S} binning={binning}")
     wl = W.small_case(order=order)
-    d, kt = _gpu_full(torch_gpu, runner, wl, wl.steps, S)
+    d, kt = _gpu_full(torch_gpu, runner, wl, wl.steps, S, binning=binning)
     from parity import compare
     res = compare(wl, wl.steps, d, np.arange(wl.num), TOL64, g_ktrace=kt)
     _say({k: v for k, v in res.items() if k != "oracle_counters"})
@@ -90,13 +93,36 @@ def test_small_case_full_run(torch_gpu, runner, order, S):
     assert kt.min() >= 0 and kt.max() >= 2
 
 
-def test_ragged_sizes(torch_gpu, runner):
+@pytest.mark.parametrize("binning", ["none", "ballot"])
+def test_ragged_sizes(torch_gpu, runner, binning):
     from parity import compare
     for num in (1, 63, 65, 1000, 4099):
-        _say(f"ragged num={num}")
+        _say(f"ragged num={num} binning={binning}")
         wl = W.make_workload("r", num, 30.0, 75, 2048, 2, 3, 0.01, 1.0, seed=num)
-        d, kt = _gpu_full(torch_gpu, runner, wl, wl.steps, 10)
+        d, kt = _gpu_full(torch_gpu, runner, wl, wl.steps, 10, binning=binning)
         compare(wl, wl.steps, d, np.arange(num), TOL64, g_ktrace=kt)
+
+
+@pytest.mark.parametrize("order", [1, 3, 5])
+def test_binning_modes_are_bitwise_identical(torch_gpu, runner, order):
+    """Which lane runs a particle must not change its arithmetic: the
+    one-lane-per-particle push and the compacted tile push agree bit for
+    bit, k traces and counters included (thermal load: uncorrelated
+    neighbours, many mixed-k tiles)."""
+    wl = W.make_workload("inv", 3000, 100.0, 75, 2048, 3, order, 0.01, 4.0, seed=31,
+                         theta=10.0 / 511.0)
+    res = {}
+    for b in ("none", "ballot"):
+        for S in (1, 37):
+            d, kt = _gpu_full(torch_gpu, runner, wl, wl.steps, S, order=order, binning=b)
+            res[(b, S)] = (d, kt)
+    ref_d, ref_kt = res[("none", 1)]
+    assert ref_kt.max() >= 3
+    for key, (d, kt) in res.items():
+        for f in ("x", "px", "py", "pz", "k_last", "status"):
+            assert np.array_equal(d[f], ref_d[f]), (key, f)
+        assert np.array_equal(kt, ref_kt), key
+        assert d["counters"] == ref_d["counters"], key
 
 
 def test_empty_particle_set(torch_gpu, runner):
@@ -143,6 +169,8 @@ def test_lost_particles_match_oracle(torch_gpu, runner):
     wl.x0[:] = wl.x_origin + (150 + 8 * np.arange(256) / 256.0) * wl.dx
     wl.x0[::7] = wl.x_origin + 0.25 * wl.dx        # outside on the left from the start
     d, kt = _gpu_full(torch_gpu, runner, wl, wl.steps, 25)
+    d2, kt2 = _gpu_full(torch_gpu, runner, wl, wl.steps, 25, binning="none")
+    assert np.array_equal(kt, kt2) and np.array_equal(d["x"], d2["x"])
     res = compare(wl, wl.steps, d, np.arange(wl.num), TOL64, g_ktrace=kt)
     assert d["counters"]["lost"] == int((d["status"] != 0).sum()) > 40
     _say(res["oracle_counters"].lost, d["counters"]["lost"])
@@ -183,9 +211,9 @@ def test_large_case_sampled(torch_gpu, runner, seed):
     torch = torch_gpu
     wl = W.large_case(seed=seed)
     steps = wl.steps
-    S = int(os.environ.get("PICSUB_BENCH_S", "250"))
+    S = int(os.environ.get("PICSUB_BENCH_S", "0")) or wl.steps
     _say(f"large case seed={seed} a0={wl.a0} steps={steps} S={S}")
-    run = runner.DeviceRun(wl, S=S)
+    run = runner.DeviceRun(wl, S=S, binning="none")
     run.reset()
     # positions are i.i.d., so a window of caller indices is a random sample
     first = int(np.random.default_rng(seed).integers(0, wl.num - 2048))
