@@ -77,13 +77,25 @@ def main():
     ap.add_argument("--seed", type=int, default=22, choices=(20, 21, 22))
     ap.add_argument("--S", type=int, default=int(os.environ.get("PICSUB_BENCH_S", "0")),
                     help="steps of dt per push launch (0: the whole run in one launch)")
-    ap.add_argument("--precision", default="fp64", choices=("fp64", "fp32c"))
+    ap.add_argument("--precision", default="fp64", choices=("fp64", "fp32c", "fp64fast"))
     ap.add_argument("--binning", default="none", choices=("none", "ballot", "learned"))
     ap.add_argument("--num", type=int, default=1 << 20)
     ap.add_argument("--periods", type=float, default=100.0)
     ap.add_argument("--cpu-every", type=int, default=64)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a device-to-device copy of BYTES (HBM counter calibration)")
     args = ap.parse_args()
+
+    if args.copy_probe:
+        import torch
+        a = torch.empty(args.copy_probe // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": a.numel() * 8}))
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the push shards by particle index with no "
@@ -151,7 +163,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "dtype": {"fp64": "f64", "fp64fast": "f64", "fp32c": "f32+f64"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"plane wave a0={wl.a0:g}, {wl.num} electrons over 8 lambda, "
                                f"T/dt=75, dx=1.01 c dt, {wl.ncells} cells, {wl.steps} steps, "
@@ -162,8 +174,9 @@ def main():
                    "n_star": counters["n_star"], "steps_by_k": counters["steps_by_k"][:9]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
-                     "kernel": ("push_wave_kernel<3>" if args.binning == "none"
-                                else "push_tile_kernel<3>"), "launches": launches,
+                     "kernel": {"fp64": "push_wave_kernel<3>", "fp64fast": "push_wave_fast_kernel<3>",
+                                "fp32c": "push_wave_mixed_kernel<3>"}[args.precision]
+                     if args.binning != "ballot" else "push_tile_kernel<3>", "launches": launches,
                      "avg_launch_ms": avg_launch_s * 1e3,
                      "flops_per_launch": flops_step * args.steps / launches},
     }

@@ -63,9 +63,18 @@ typedef enum { PIC_MEM_HOST = 0, PIC_MEM_DEVICE = 1 } pic_mem;
 
 /* arithmetic of the push */
 typedef enum {
-    PIC_FP64 = 0,       /* everything in FP64 */
-    PIC_FP32_COMP = 1   /* FP32 bulk with compensated x and p; FP64
-                           weights, decision and sub-cycled steps */
+    PIC_FP64 = 0,       /* IEEE FP64 in the operation order of the equations:
+                           bit-identical to a plain scalar implementation */
+    PIC_FP32_COMP = 1,  /* k = 0 steps in FP32 (FP32 fields and Boris update,
+                           p as FP32 hi/lo pairs with TwoSum, x as node index +
+                           FP32 fraction + carry); FP64 weights and sub-cycled
+                           steps.  Not within 1e-5 of FP64 for ultra-
+                           relativistic electrons (gamma amplifies FP32
+                           rounding of the transverse force) */
+    PIC_FP64_FAST = 2   /* FP64 with hardware reciprocal / rsqrt estimates
+                           refined by Newton steps (faithful rounding),
+                           positions in node units, 1/gamma reused by the
+                           next decision */
 } pic_precision;
 
 /* how particles are grouped onto wavefronts for the sub-step loop */

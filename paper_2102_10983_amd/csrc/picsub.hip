@@ -1037,6 +1037,533 @@ __global__ void __launch_bounds__(64) push_wave_kernel(WaveArgs a)
     flush_counts_atomic(cnt, a.cnt + int64_t(blockIdx.x % a.nslot) * NCNT);
 }
 
+// ---------------------------------------------------------------------
+// FP32 bulk push with compensated state, FP64 sub-cycled steps
+// (pic_precision PIC_FP32_COMP).
+//
+// Registers hold x as an int32 node index `cell`, an FP32 fraction `fr`
+// of a cell and its FP32 carry, and each momentum component as an FP32
+// pair (hi, lo).  A step with k = 0 runs in FP32: the fields come from
+// the FP64 temporal combination rounded once to FP32, the Boris update is
+// formed as increments of p that are added to (hi, lo) with TwoSum, and
+// the position increment uses 1 - v = (1 + p_y^2 + p_z^2) / (gamma
+// (gamma + |p_x|)), free of cancellation for ultra-relativistic
+// electrons.  A step with k >= 1 (the stopping points, where gamma is near
+// 1) is done entirely in FP64 with the FP64 weights, in node units, then
+// split back.  The state in HBM stays FP64: a launch converts on entry
+// and on exit.
+// ---------------------------------------------------------------------
+__device__ __forceinline__ void two_sum(float a, float b, float &s, float &e)
+{
+    s = a + b;
+    const float bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+// (hi, lo) += d
+__device__ __forceinline__ void comp_add(float &hi, float &lo, float d)
+{
+    const float y = d + lo;
+    float s, e;
+    two_sum(hi, y, s, e);
+    hi = s;
+    lo = e;
+}
+
+__device__ __forceinline__ void split(double v, float &hi, float &lo)
+{
+    hi = float(v);
+    lo = float(v - double(hi));
+}
+
+// 1 / b: hardware estimate and two Newton steps
+__device__ __forceinline__ double rcp_nr(double b)
+{
+    double r = __builtin_amdgcn_rcp(b);
+    double e = fma(-b, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-b, r, 1.0);
+    return fma(r, e, r);
+}
+
+// 1 / sqrt(a), a >= 1: hardware estimate and two Newton steps
+__device__ __forceinline__ double rsq_nr(double a)
+{
+    double y = __builtin_amdgcn_rsq(a);
+    double h = 0.5 * a;
+    double r = fma(-h * y, y, 0.5);
+    y = fma(y, r, y);
+    r = fma(-h * y, y, 0.5);
+    return fma(y, r, y);
+}
+
+__device__ __forceinline__ void boris_fast(double qm, double dtp, double E, double B, double &px,
+                                           double &py, double &pz)
+{
+    const double c = 0.5 * qm * dtp;
+    const double h = c * E;
+    const double mx = px, my = py + h, mz = pz;
+    const double ig = rsq_nr(1.0 + ((mx * mx + my * my) + mz * mz));
+    const double t = (c * B) * ig;
+    const double sz = (2.0 * t) * rcp_nr(1.0 + t * t);
+    const double ax = mx + my * t;
+    const double ay = my - mx * t;
+    px = mx + ay * sz;
+    py = (my - ax * sz) + h;
+    pz = mz;
+}
+
+struct MixArgs {
+    WaveArgs w;
+    float dtdx_hi, dtdx_lo;      // dt / dx as an FP32 pair
+    double dtdx;                 // dt / dx
+};
+
+template <int P>
+__global__ void __launch_bounds__(64) push_wave_mixed_kernel(MixArgs ma)
+{
+    const WaveArgs &a = ma.w;
+    constexpr int STRIDE = 2 * (P + 1);
+    __shared__ double sE[(P + 1) * WWIN];
+    __shared__ double sB[(P + 1) * WWIN];
+    __shared__ float sBh[WWIN];          // B at s = 1/2, FP64 combination rounded
+    __shared__ float sEn[WWIN];          // E at level n
+    const int lane = threadIdx.x;
+    const int ncm2 = a.ncells - 2;
+    const double *W1 = a.wtab;
+    const float c0f = float(0.5 * a.qm * a.dt);
+    const float psif = float(a.psi_max);
+    Counts cnt;
+    cnt.zero();
+
+    const int64_t i = int64_t(blockIdx.x) * 64 + lane;
+    const bool mine = i < a.np;
+    int cell = 0;
+    float fr = 0.f, frc = 0.f, pxh = 0.f, pxl = 0.f, pyh = 0.f, pyl = 0.f, pzh = 0.f, pzl = 0.f;
+    int kold = 0;
+    uint8_t status = PIC_PARTICLE_LOST;
+    int64_t kt_u = -1;
+    if (mine) {
+        const double xi = (a.x[i] - a.x_origin) / a.dx;
+        status = a.status[i];
+        if (status == PIC_PARTICLE_LIVE && xi >= 0.0 && xi < double(a.ncells)) {
+            const double fl = floor(xi);
+            cell = int(fl);
+            split(xi - fl, fr, frc);
+        } else if (status == PIC_PARTICLE_LIVE) {
+            cell = -1;     // outside: flagged at the first step
+        }
+        split(a.px[i], pxh, pxl);
+        split(a.py[i], pyh, pyl);
+        split(a.pz[i], pzh, pzl);
+        kold = a.kold[i];
+        if (a.ktrace) {
+            const int64_t u = a.perm[i] - a.kt_first;
+            if (u >= 0 && u < a.kt_count) kt_u = u;
+        }
+    }
+    bool moved = false;      // the FP64 state must be rewritten
+
+    for (int st = 0; st < a.S; ++st) {
+        WaveLevels<P> lv;
+        lv.at(a, st);
+        const bool live = status == PIC_PARTICLE_LIVE && cell >= 0 && cell <= ncm2 &&
+                          (cell > 0 || fr >= 0.5f);
+        if (status == PIC_PARTICLE_LIVE && !live) {
+            status = PIC_PARTICLE_LOST;
+            ++cnt.lost;
+        }
+        if (!live && kt_u >= 0) {
+            const int64_t r = a.n0 + st - a.kt_n0;
+            if (r >= 0 && r < a.kt_steps) a.ktrace[r * a.kt_count + kt_u] = -1;
+        }
+        if (!__any(live)) {
+            if (kt_u >= 0)
+                for (int s2 = st + 1; s2 < a.S; ++s2) {
+                    const int64_t r = a.n0 + s2 - a.kt_n0;
+                    if (r >= 0 && r < a.kt_steps) a.ktrace[r * a.kt_count + kt_u] = -1;
+                }
+            break;
+        }
+        const int lo = max(wave_min(live ? cell - a.margin : INT_MAX), 0);
+        const int hi = min(wave_max(live ? cell + a.margin : INT_MIN), a.ncells - 1);
+        const bool use_lds = hi - lo + 1 <= WWIN;
+        if (use_lds) {
+            __syncthreads();
+            for (int q = lane; q <= hi - lo; q += 64) {
+                const double b = node_comb<P>(a.ringB, lv.off, lo + q, W1 + P + 1);
+                sBh[q] = float(b);
+                sEn[q] = float(a.ringE[lv.off[P] + lo + q]);
+            }
+            __syncthreads();
+        }
+
+        // decision in FP32: B at (x_n, s = 1/2), gamma of the stored p
+        int k = 0;
+        float Bd = 0.f;
+        float wB = fr, wE;
+        int iE;
+        if (fr >= 0.5f) {
+            iE = cell;
+            wE = fr - 0.5f;
+        } else {
+            iE = cell - 1;
+            wE = fr + 0.5f;
+        }
+        if (live) {
+            float b0, b1;
+            if (use_lds) {
+                b0 = sBh[cell - lo];
+                b1 = sBh[cell + 1 - lo];
+            } else {
+                b0 = float(node_comb<P>(a.ringB, lv.off, cell, W1 + P + 1));
+                b1 = float(node_comb<P>(a.ringB, lv.off, cell + 1, W1 + P + 1));
+            }
+            Bd = (1.f - wB) * b0 + wB * b1;
+            const float p2 = (pxh * pxh + pyh * pyh) + pzh * pzh;
+            const float psi0 = fabsf(c0f * Bd) * __builtin_amdgcn_rsqf(1.f + p2);
+            float lim = psif;
+            while (psi0 > lim && k < a.kmax) {
+                ++k;
+                lim = lim * 4.f;
+            }
+            cnt.clamps += psi0 > lim;
+            if (kt_u >= 0) {
+                const int64_t r = a.n0 + st - a.kt_n0;
+                if (r >= 0 && r < a.kt_steps) a.ktrace[r * a.kt_count + kt_u] = int8_t(k);
+            }
+        }
+        const bool heavy = live && k > 0;
+        // raw FP64 levels for the sub-cycled steps
+        const bool any_heavy = __any(heavy);
+        if (any_heavy && use_lds) {
+            __syncthreads();
+            for (int q = lane; q <= hi - lo; q += 64) {
+#pragma unroll
+                for (int j = 0; j <= P; ++j) {
+                    sE[j * WWIN + q] = a.ringE[lv.off[j] + lo + q];
+                    sB[j * WWIN + q] = a.ringB[lv.off[j] + lo + q];
+                }
+            }
+            __syncthreads();
+        }
+        if (!live) continue;
+        moved = true;
+        const int ko = kold < 0 ? k : kold;
+        kold = k;
+        if (!heavy) {
+            // ---- k = 0 in FP32 with compensated accumulation
+            float e0, e1;
+            if (use_lds) {
+                e0 = sEn[iE - lo];
+                e1 = sEn[iE + 1 - lo];
+            } else {
+                e0 = float(a.ringE[lv.off[P] + iE]);
+                e1 = float(a.ringE[lv.off[P] + iE + 1]);
+            }
+            const float E = (1.f - wE) * e0 + wE * e1;
+            const float cf = float(0.5 * a.qm * (0.5 * (ldexp(a.dt, -2 * ko) + a.dt)));
+            const float h = cf * E;
+            const float mx = pxh, my = pyh + h, mz = pzh;
+            const float ig = __builtin_amdgcn_rsqf(1.f + ((mx * mx + my * my) + mz * mz));
+            const float t = cf * Bd * ig;
+            const float sz = 2.f * t * __builtin_amdgcn_rcpf(1.f + t * t);
+            const float ax = mx + my * t;
+            const float ay = my - mx * t;
+            comp_add(pxh, pxl, ay * sz);
+            comp_add(pyh, pyl, (h + h) - ax * sz);
+            // position: v = p_x / gamma, with 1 - |v| formed without cancellation
+            const float q2 = (pyh * pyh + pzh * pzh);
+            const float g2 = __builtin_amdgcn_sqrtf(1.f + (pxh * pxh + q2));
+            const float apx = fabsf(pxh);
+            const float omv = (1.f + q2) * __builtin_amdgcn_rcpf(g2 * (g2 + apx));   // 1 - |v|
+            // dfr = (dt/dx) v = sign(p_x) ((dt/dx) - (dt/dx)(1 - |v|))
+            const float sgn = pxh < 0.f ? -1.f : 1.f;
+            const float small = ma.dtdx_hi * omv;
+            float y = sgn * ((ma.dtdx_lo - small) + 0.f);
+            // fr + sgn*dtdx_hi is the large part; add the small part to the carry
+            float s, e;
+            two_sum(fr, sgn * ma.dtdx_hi, s, e);
+            y = y + e + frc;
+            float s2, e2;
+            two_sum(s, y, s2, e2);
+            // back into [0, 1)
+            const float adj = s2 >= 1.f ? -1.f : (s2 < 0.f ? 1.f : 0.f);
+            cell -= int(adj);
+            two_sum(s2, adj, fr, e);
+            frc = e2 + e;
+            cnt.step_done(0);
+        } else {
+            // ---- sub-cycled step in FP64, node units
+            double xi = double(cell) + (double(fr) + double(frc));
+            double px = double(pxh) + double(pxl);
+            double py = double(pyh) + double(pyl);
+            double pz = double(pzh) + double(pzl);
+            const double dt_new = ldexp(a.dt, -2 * k);
+            const double dt_old = ldexp(a.dt, -2 * ko);
+            const double rdx = ldexp(ma.dtdx, -2 * k);
+            const int nsub = 1 << (2 * k);
+            const double *Wk = a.wtab + wtab_offset(k) * STRIDE;
+            int32_t vo[P + 1];
+#pragma unroll
+            for (int j = 0; j <= P; ++j) vo[j] = j * WWIN - lo;
+            const double ncm1 = double(a.ncells - 1);
+            bool done = true;
+            for (int j = 1; j <= nsub; ++j, Wk += STRIDE) {
+                if (!(xi >= 0.5 && xi < ncm1)) {
+                    done = false;
+                    break;
+                }
+                const double fl = floor(xi);
+                const int ib = int(fl);
+                const double wb = xi - fl;
+                const double uE = xi - 0.5;
+                const double flE = floor(uE);
+                const int ie = int(flE);
+                const double we = uE - flE;
+                double b0, b1, e0, e1;
+                if (use_lds) {
+                    b0 = node_comb<P>(sB, vo, ib, Wk + P + 1);
+                    b1 = node_comb<P>(sB, vo, ib + 1, Wk + P + 1);
+                    e0 = node_comb<P>(sE, vo, ie, Wk);
+                    e1 = node_comb<P>(sE, vo, ie + 1, Wk);
+                } else {
+                    b0 = node_comb<P>(a.ringB, lv.off, ib, Wk + P + 1);
+                    b1 = node_comb<P>(a.ringB, lv.off, ib + 1, Wk + P + 1);
+                    e0 = node_comb<P>(a.ringE, lv.off, ie, Wk);
+                    e1 = node_comb<P>(a.ringE, lv.off, ie + 1, Wk);
+                }
+                const double B = (1.0 - wb) * b0 + wb * b1;
+                const double E = (1.0 - we) * e0 + we * e1;
+                const double dtp = j == 1 ? 0.5 * (dt_old + dt_new) : dt_new;
+                boris(a.qm, dtp, E, B, px, py, pz);
+                const double g2 = sqrt(1.0 + ((px * px + py * py) + pz * pz));
+                xi = xi + rdx * (px / g2);
+            }
+            if (done) {
+                cnt.step_done(k);
+            } else {
+                status = PIC_PARTICLE_LOST;
+                ++cnt.lost;
+            }
+            const double fl = floor(xi);
+            cell = (xi >= 0.0 && xi < double(a.ncells)) ? int(fl) : -1;
+            split(xi - fl, fr, frc);
+            split(px, pxh, pxl);
+            split(py, pyh, pyl);
+            split(pz, pzh, pzl);
+        }
+    }
+    if (mine) {
+        if (moved) {
+            const double xi = double(cell) + (double(fr) + double(frc));
+            a.x[i] = a.x_origin + xi * a.dx;
+            a.px[i] = double(pxh) + double(pxl);
+            a.py[i] = double(pyh) + double(pyl);
+            a.pz[i] = double(pzh) + double(pzl);
+        }
+        a.kold[i] = int8_t(kold);
+        a.status[i] = status;
+    }
+    flush_counts_atomic(cnt, a.cnt + int64_t(blockIdx.x % a.nslot) * NCNT);
+}
+
+// ---------------------------------------------------------------------
+// Fast FP64 push (pic_precision PIC_FP64_FAST).
+//
+// The same method in FP64 throughout, with three changes of evaluation
+// that move results by rounding only: the reciprocal and the reciprocal
+// square root use the hardware estimates refined by two Newton steps
+// (faithfully rounded) in place of the IEEE division and square-root
+// sequences; the position is carried in node units xi = (x - x_origin) / dx,
+// so a step needs no division by dx; and 1 / gamma of the stored momentum,
+// computed by the previous step's position update, is reused by the next
+// step's decision.
+// ---------------------------------------------------------------------
+template <int P>
+__global__ void __launch_bounds__(64) push_wave_fast_kernel(MixArgs ma)
+{
+    const WaveArgs &a = ma.w;
+    constexpr int STRIDE = 2 * (P + 1);
+    __shared__ double sE[(P + 1) * WWIN];
+    __shared__ double sB[(P + 1) * WWIN];
+    __shared__ double sBh[WWIN];
+    const int lane = threadIdx.x;
+    const double ncm1 = double(a.ncells - 1);
+    const double c0 = 0.5 * a.qm * a.dt;
+    const double *W1 = a.wtab;
+    Counts cnt;
+    cnt.zero();
+
+    const int64_t i = int64_t(blockIdx.x) * 64 + lane;
+    const bool mine = i < a.np;
+    double xi = 0, px = 0, py = 0, pz = 0, ig = 1;
+    int kold = 0;
+    uint8_t status = PIC_PARTICLE_LOST;
+    int64_t kt_u = -1;
+    if (mine) {
+        xi = (a.x[i] - a.x_origin) / a.dx;
+        px = a.px[i];
+        py = a.py[i];
+        pz = a.pz[i];
+        ig = rsq_nr(1.0 + ((px * px + py * py) + pz * pz));
+        kold = a.kold[i];
+        status = a.status[i];
+        if (a.ktrace) {
+            const int64_t u = a.perm[i] - a.kt_first;
+            if (u >= 0 && u < a.kt_count) kt_u = u;
+        }
+    }
+    bool moved = false;
+
+    for (int st = 0; st < a.S; ++st) {
+        WaveLevels<P> lv;
+        lv.at(a, st);
+        const bool live = status == PIC_PARTICLE_LIVE && xi >= 0.5 && xi < ncm1;
+        if (status == PIC_PARTICLE_LIVE && !live) {
+            status = PIC_PARTICLE_LOST;
+            ++cnt.lost;
+        }
+        if (!live && kt_u >= 0) {
+            const int64_t r = a.n0 + st - a.kt_n0;
+            if (r >= 0 && r < a.kt_steps) a.ktrace[r * a.kt_count + kt_u] = -1;
+        }
+        if (!__any(live)) {
+            if (kt_u >= 0)
+                for (int s2 = st + 1; s2 < a.S; ++s2) {
+                    const int64_t r = a.n0 + s2 - a.kt_n0;
+                    if (r >= 0 && r < a.kt_steps) a.ktrace[r * a.kt_count + kt_u] = -1;
+                }
+            break;
+        }
+        const double flB = live ? floor(xi) : 0.0;
+        const int cell = int(flB);
+        const int lo = max(wave_min(live ? cell - a.margin : INT_MAX), 0);
+        const int hi = min(wave_max(live ? cell + a.margin : INT_MIN), a.ncells - 1);
+        const bool use_lds = hi - lo + 1 <= WWIN;
+        if (use_lds) {
+            __syncthreads();
+            for (int q = lane; q <= hi - lo; q += 64) {
+                double bh = 0;
+#pragma unroll
+                for (int j = 0; j <= P; ++j) {
+                    const double e = a.ringE[lv.off[j] + lo + q];
+                    const double b = a.ringB[lv.off[j] + lo + q];
+                    sE[j * WWIN + q] = e;
+                    sB[j * WWIN + q] = b;
+                    bh = j == 0 ? W1[P + 1] * b : bh + W1[P + 1 + j] * b;
+                }
+                sBh[q] = bh;
+            }
+            __syncthreads();
+        }
+        int32_t vo[P + 1];
+#pragma unroll
+        for (int j = 0; j <= P; ++j) vo[j] = j * WWIN - lo;
+        if (!live) continue;
+        moved = true;
+
+        const double wB = xi - flB;
+        double b0, b1;
+        if (use_lds) {
+            b0 = sBh[cell - lo];
+            b1 = sBh[cell + 1 - lo];
+        } else {
+            b0 = node_comb<P>(a.ringB, lv.off, cell, W1 + P + 1);
+            b1 = node_comb<P>(a.ringB, lv.off, cell + 1, W1 + P + 1);
+        }
+        const double Bd = (1.0 - wB) * b0 + wB * b1;
+        const double psi0 = fabs(c0 * Bd) * ig;
+        int k = 0;
+        double lim = a.psi_max;
+        while (psi0 > lim && k < a.kmax) {
+            ++k;
+            lim = lim * 4.0;
+        }
+        cnt.clamps += psi0 > lim;
+        if (kt_u >= 0) {
+            const int64_t r = a.n0 + st - a.kt_n0;
+            if (r >= 0 && r < a.kt_steps) a.ktrace[r * a.kt_count + kt_u] = int8_t(k);
+        }
+        const int ko = kold < 0 ? k : kold;
+        kold = k;
+        const double dt_new = ldexp(a.dt, -2 * k);
+        const double dt_old = ldexp(a.dt, -2 * ko);
+        const double rdx = ldexp(ma.dtdx, -2 * k);
+        if (k == 0) {
+            const double uE = xi - 0.5;
+            const double flE = floor(uE);
+            const int iE = int(flE);
+            const double wE = uE - flE;
+            double e0, e1;
+            if (use_lds) {
+                e0 = sE[vo[P] + iE];
+                e1 = sE[vo[P] + iE + 1];
+            } else {
+                e0 = a.ringE[lv.off[P] + iE];
+                e1 = a.ringE[lv.off[P] + iE + 1];
+            }
+            const double E = (1.0 - wE) * e0 + wE * e1;
+            boris_fast(a.qm, 0.5 * (dt_old + dt_new), E, Bd, px, py, pz);
+            ig = rsq_nr(1.0 + ((px * px + py * py) + pz * pz));
+            xi = xi + rdx * (px * ig);
+            cnt.step_done(0);
+        } else {
+            const int nsub = 1 << (2 * k);
+            const double *Wk = a.wtab + wtab_offset(k) * STRIDE;
+            bool done = true;
+            for (int j = 1; j <= nsub; ++j, Wk += STRIDE) {
+                if (!(xi >= 0.5 && xi < ncm1)) {
+                    done = false;
+                    break;
+                }
+                const double fl = floor(xi);
+                const int ib = int(fl);
+                const double wb = xi - fl;
+                const double uE = xi - 0.5;
+                const double flE = floor(uE);
+                const int ie = int(flE);
+                const double we = uE - flE;
+                double bb0, bb1, e0, e1;
+                if (use_lds) {
+                    bb0 = node_comb<P>(sB, vo, ib, Wk + P + 1);
+                    bb1 = node_comb<P>(sB, vo, ib + 1, Wk + P + 1);
+                    e0 = node_comb<P>(sE, vo, ie, Wk);
+                    e1 = node_comb<P>(sE, vo, ie + 1, Wk);
+                } else {
+                    bb0 = node_comb<P>(a.ringB, lv.off, ib, Wk + P + 1);
+                    bb1 = node_comb<P>(a.ringB, lv.off, ib + 1, Wk + P + 1);
+                    e0 = node_comb<P>(a.ringE, lv.off, ie, Wk);
+                    e1 = node_comb<P>(a.ringE, lv.off, ie + 1, Wk);
+                }
+                const double B = (1.0 - wb) * bb0 + wb * bb1;
+                const double E = (1.0 - we) * e0 + we * e1;
+                const double dtp = j == 1 ? 0.5 * (dt_old + dt_new) : dt_new;
+                boris_fast(a.qm, dtp, E, B, px, py, pz);
+                ig = rsq_nr(1.0 + ((px * px + py * py) + pz * pz));
+                xi = xi + rdx * (px * ig);
+            }
+            if (done) {
+                cnt.step_done(k);
+            } else {
+                status = PIC_PARTICLE_LOST;
+                ++cnt.lost;
+            }
+        }
+    }
+    if (mine) {
+        if (moved) {
+            a.x[i] = a.x_origin + xi * a.dx;
+            a.px[i] = px;
+            a.py[i] = py;
+            a.pz[i] = pz;
+        }
+        a.kold[i] = int8_t(kold);
+        a.status[i] = status;
+    }
+    flush_counts_atomic(cnt, a.cnt + int64_t(blockIdx.x % a.nslot) * NCNT);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------
@@ -1135,10 +1662,13 @@ pic_status check_params(pic_ctx *ctx, const pic_params *p, int64_t np)
     if (!(p->psi_max > 0)) return fail(ctx, PIC_E_ARG, "psi_max must be > 0");
     if (!(p->qm != 0) || p->qm != p->qm) return fail(ctx, PIC_E_ARG, "qm must be nonzero");
     if (p->x_origin != p->x_origin) return fail(ctx, PIC_E_ARG, "x_origin is NaN");
-    if (p->precision != PIC_FP64 && p->precision != PIC_FP32_COMP)
+    if (p->precision != PIC_FP64 && p->precision != PIC_FP32_COMP &&
+        p->precision != PIC_FP64_FAST)
         return fail(ctx, PIC_E_ARG, "unknown precision %d", p->precision);
     if (p->binning < PIC_BIN_NONE || p->binning > PIC_BIN_LEARNED)
         return fail(ctx, PIC_E_ARG, "unknown binning %d", p->binning);
+    if (p->precision != PIC_FP64 && p->binning == PIC_BIN_BALLOT)
+        return fail(ctx, PIC_E_ARG, "the tiled ballot push runs with PIC_FP64 only");
     if (int64_t(p->ring_depth) * p->ncells >= (int64_t(1) << 31))
         return fail(ctx, PIC_E_ARG, "ring_depth * ncells must stay below 2^31");
     if (int64_t(p->ncells) * SORT_SUB >= (int64_t(1) << 30))
@@ -1442,10 +1972,29 @@ pic_status pic_push_subcycled(pic_ctx *ctx, int64_t n, int32_t S)
         wa.slot0 = slot0;
         wa.margin = margin;
         const dim3 grid(unsigned((ctx->np + 63) / 64)), block(64);
-        switch (p.order) {
-        case 1: push_wave_kernel<1><<<grid, block, 0, ctx->stream>>>(wa); break;
-        case 3: push_wave_kernel<3><<<grid, block, 0, ctx->stream>>>(wa); break;
-        default: push_wave_kernel<5><<<grid, block, 0, ctx->stream>>>(wa); break;
+        MixArgs ma;
+        ma.w = wa;
+        ma.dtdx = p.dt / p.dx;
+        ma.dtdx_hi = float(ma.dtdx);
+        ma.dtdx_lo = float(ma.dtdx - double(ma.dtdx_hi));
+        if (p.precision == PIC_FP32_COMP) {
+            switch (p.order) {
+            case 1: push_wave_mixed_kernel<1><<<grid, block, 0, ctx->stream>>>(ma); break;
+            case 3: push_wave_mixed_kernel<3><<<grid, block, 0, ctx->stream>>>(ma); break;
+            default: push_wave_mixed_kernel<5><<<grid, block, 0, ctx->stream>>>(ma); break;
+            }
+        } else if (p.precision == PIC_FP64_FAST) {
+            switch (p.order) {
+            case 1: push_wave_fast_kernel<1><<<grid, block, 0, ctx->stream>>>(ma); break;
+            case 3: push_wave_fast_kernel<3><<<grid, block, 0, ctx->stream>>>(ma); break;
+            default: push_wave_fast_kernel<5><<<grid, block, 0, ctx->stream>>>(ma); break;
+            }
+        } else {
+            switch (p.order) {
+            case 1: push_wave_kernel<1><<<grid, block, 0, ctx->stream>>>(wa); break;
+            case 3: push_wave_kernel<3><<<grid, block, 0, ctx->stream>>>(wa); break;
+            default: push_wave_kernel<5><<<grid, block, 0, ctx->stream>>>(wa); break;
+            }
         }
         LAUNCH_CHECK(ctx);
         return PIC_OK;

@@ -19,7 +19,7 @@ PIC_KHIST = 16
 PIC_K_MAX_LIMIT = 8
 STATUS = {0: "PIC_OK", 1: "PIC_E_ARG", 2: "PIC_E_DEVICE", 3: "PIC_E_NOMEM",
           4: "PIC_E_LEVEL", 5: "PIC_E_STATE"}
-PRECISION = {"fp64": 0, "fp32c": 1}
+PRECISION = {"fp64": 0, "fp32c": 1, "fp64fast": 2}
 BINNING = {"none": 0, "ballot": 1, "learned": 2}
 MEM_HOST, MEM_DEVICE = 0, 1
 
