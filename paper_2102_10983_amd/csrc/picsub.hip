@@ -1387,11 +1387,13 @@ __global__ void __launch_bounds__(64) push_wave_fast_kernel(MixArgs ma)
     constexpr int STRIDE = 2 * (P + 1);
     __shared__ double sE[(P + 1) * WWIN];
     __shared__ double sB[(P + 1) * WWIN];
-    __shared__ double sBh[WWIN];
     const int lane = threadIdx.x;
     const double ncm1 = double(a.ncells - 1);
     const double c0 = 0.5 * a.qm * a.dt;
     const double *W1 = a.wtab;
+    double LB1[P + 1];                 // B weights at s = 1/2
+#pragma unroll
+    for (int j = 0; j <= P; ++j) LB1[j] = W1[P + 1 + j];
     Counts cnt;
     cnt.zero();
 
@@ -1436,55 +1438,51 @@ __global__ void __launch_bounds__(64) push_wave_fast_kernel(MixArgs ma)
                 }
             break;
         }
-        const double flB = live ? floor(xi) : 0.0;
-        const int cell = int(flB);
-        const int lo = max(wave_min(live ? cell - a.margin : INT_MAX), 0);
-        const int hi = min(wave_max(live ? cell + a.margin : INT_MIN), a.ncells - 1);
-        const bool use_lds = hi - lo + 1 <= WWIN;
-        if (use_lds) {
-            __syncthreads();
-            for (int q = lane; q <= hi - lo; q += 64) {
-                double bh = 0;
-#pragma unroll
-                for (int j = 0; j <= P; ++j) {
-                    const double e = a.ringE[lv.off[j] + lo + q];
-                    const double b = a.ringB[lv.off[j] + lo + q];
-                    sE[j * WWIN + q] = e;
-                    sB[j * WWIN + q] = b;
-                    bh = j == 0 ? W1[P + 1] * b : bh + W1[P + 1 + j] * b;
-                }
-                sBh[q] = bh;
+        // decision from B at (x_n, s = 1/2), gathered straight from the ring
+        int k = 0;
+        int cell = 0;
+        double Bd = 0.0;
+        if (live) {
+            const double flB = floor(xi);
+            cell = int(flB);
+            const double wB = xi - flB;
+            const double b0 = node_comb<P>(a.ringB, lv.off, cell, LB1);
+            const double b1 = node_comb<P>(a.ringB, lv.off, cell + 1, LB1);
+            Bd = (1.0 - wB) * b0 + wB * b1;
+            const double psi0 = fabs(c0 * Bd) * ig;
+            double lim = a.psi_max;
+            while (psi0 > lim && k < a.kmax) {
+                ++k;
+                lim = lim * 4.0;
             }
-            __syncthreads();
+            cnt.clamps += psi0 > lim;
+            if (kt_u >= 0) {
+                const int64_t r = a.n0 + st - a.kt_n0;
+                if (r >= 0 && r < a.kt_steps) a.ktrace[r * a.kt_count + kt_u] = int8_t(k);
+            }
         }
-        int32_t vo[P + 1];
+        const bool heavy = live && k > 0;
+        // sub-cycled lanes: stage their node window once for all sub-steps
+        bool use_lds = false;
+        int lo = 0;
+        if (__any(heavy)) {
+            lo = max(wave_min(heavy ? cell - a.margin : INT_MAX), 0);
+            const int hi = min(wave_max(heavy ? cell + a.margin : INT_MIN), a.ncells - 1);
+            use_lds = hi - lo + 1 <= WWIN;
+            if (use_lds) {
+                __syncthreads();
+                for (int q = lane; q <= hi - lo; q += 64) {
 #pragma unroll
-        for (int j = 0; j <= P; ++j) vo[j] = j * WWIN - lo;
+                    for (int j = 0; j <= P; ++j) {
+                        sE[j * WWIN + q] = a.ringE[lv.off[j] + lo + q];
+                        sB[j * WWIN + q] = a.ringB[lv.off[j] + lo + q];
+                    }
+                }
+                __syncthreads();
+            }
+        }
         if (!live) continue;
         moved = true;
-
-        const double wB = xi - flB;
-        double b0, b1;
-        if (use_lds) {
-            b0 = sBh[cell - lo];
-            b1 = sBh[cell + 1 - lo];
-        } else {
-            b0 = node_comb<P>(a.ringB, lv.off, cell, W1 + P + 1);
-            b1 = node_comb<P>(a.ringB, lv.off, cell + 1, W1 + P + 1);
-        }
-        const double Bd = (1.0 - wB) * b0 + wB * b1;
-        const double psi0 = fabs(c0 * Bd) * ig;
-        int k = 0;
-        double lim = a.psi_max;
-        while (psi0 > lim && k < a.kmax) {
-            ++k;
-            lim = lim * 4.0;
-        }
-        cnt.clamps += psi0 > lim;
-        if (kt_u >= 0) {
-            const int64_t r = a.n0 + st - a.kt_n0;
-            if (r >= 0 && r < a.kt_steps) a.ktrace[r * a.kt_count + kt_u] = int8_t(k);
-        }
         const int ko = kold < 0 ? k : kold;
         kold = k;
         const double dt_new = ldexp(a.dt, -2 * k);
@@ -1495,20 +1493,20 @@ __global__ void __launch_bounds__(64) push_wave_fast_kernel(MixArgs ma)
             const double flE = floor(uE);
             const int iE = int(flE);
             const double wE = uE - flE;
-            double e0, e1;
-            if (use_lds) {
-                e0 = sE[vo[P] + iE];
-                e1 = sE[vo[P] + iE + 1];
-            } else {
-                e0 = a.ringE[lv.off[P] + iE];
-                e1 = a.ringE[lv.off[P] + iE + 1];
-            }
+            const double e0 = a.ringE[lv.off[P] + iE];
+            const double e1 = a.ringE[lv.off[P] + iE + 1];
             const double E = (1.0 - wE) * e0 + wE * e1;
             boris_fast(a.qm, 0.5 * (dt_old + dt_new), E, Bd, px, py, pz);
             ig = rsq_nr(1.0 + ((px * px + py * py) + pz * pz));
             xi = xi + rdx * (px * ig);
             cnt.step_done(0);
         } else {
+            // the longest dependency chains of the launch: let this
+            // wavefront issue ahead of those doing single steps
+            __builtin_amdgcn_s_setprio(2);
+            int32_t vo[P + 1];
+#pragma unroll
+            for (int j = 0; j <= P; ++j) vo[j] = j * WWIN - lo;
             const int nsub = 1 << (2 * k);
             const double *Wk = a.wtab + wtab_offset(k) * STRIDE;
             bool done = true;
@@ -1543,6 +1541,7 @@ __global__ void __launch_bounds__(64) push_wave_fast_kernel(MixArgs ma)
                 ig = rsq_nr(1.0 + ((px * px + py * py) + pz * pz));
                 xi = xi + rdx * (px * ig);
             }
+            __builtin_amdgcn_s_setprio(0);
             if (done) {
                 cnt.step_done(k);
             } else {
