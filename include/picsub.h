@@ -185,10 +185,90 @@ pic_status pic_diag(pic_ctx *ctx, pic_mem mem, double *gamma, double *px,
 /* Reset the counters to zero (asynchronous). */
 pic_status pic_counters_reset(pic_ctx *ctx);
 
-/* Tuning knobs of the push launch (0 keeps the current value):
- * block = threads per workgroup (64..1024, multiple of 64);
- * tile  = particles per compaction tile (multiple of block). */
-pic_status pic_tune_set(pic_ctx *ctx, int32_t block, int32_t tile);
+/* ------------------------------------------------------------------ */
+/* Batches of independent runs.                                        */
+/* ------------------------------------------------------------------ */
+
+/* A context holding nruns independent runs, each with its own grid,
+ * dt, psi_max, field ring (per_run[r]) and np[r] particles.  The runs
+ * share order, precision and binning.  Caller particle arrays list the
+ * runs' particles one run after the other (run 0 first).  pic_create is
+ * the one-run case.  Calls without a run index act on every run (field
+ * loads without an index act on run 0). */
+pic_status pic_batch_create(const pic_params *per_run, const int64_t *np,
+                            int32_t nruns, void *hip_stream, pic_ctx **out);
+
+/* Field loads of one run (see pic_fields_load, pic_fields_load_lattice). */
+pic_status pic_fields_load_r(pic_ctx *ctx, int32_t run, int64_t n, pic_mem mem,
+                             const double *Ey, const double *Bz);
+pic_status pic_fields_load_lattice_r(pic_ctx *ctx, int32_t run,
+                                     int64_t n_first, int32_t count,
+                                     const double *table, int64_t M,
+                                     int64_t aE, int64_t bE, int64_t cE,
+                                     int64_t aB, int64_t bB, int64_t cB);
+
+/* Device-driven mode.  Attach a phase table (device array of M doubles,
+ * coefficients as in pic_fields_load_lattice, kept valid by the caller)
+ * to a run whose particles sit at level n_start and which stops at level
+ * n_stop (INT64_MAX: never); the levels n_start - order .. n_start - 1
+ * are sampled now.  From then on pic_advance moves every run on by S of
+ * its own steps (fewer once it reaches n_stop): it samples the new levels
+ * of each run on the device, pushes (Algorithm 1, Sec. IV) and moves the
+ * run's level counter, all without host state, so windows can be captured
+ * into a graph.  Requires a source on every run and S + order <=
+ * ring_depth of every run. */
+pic_status pic_source_set(pic_ctx *ctx, int32_t run, int64_t n_start,
+                          int64_t n_stop, const double *table, int64_t M,
+                          int64_t aE, int64_t bE, int64_t cE, int64_t aB,
+                          int64_t bB, int64_t cB);
+pic_status pic_advance(pic_ctx *ctx, int32_t S);
+
+/* Level the run will have reached when the queued work is done. */
+pic_status pic_run_level(const pic_ctx *ctx, int32_t run, int64_t *n);
+
+/* Capture `windows` consecutive pic_advance(S) calls into a HIP graph
+ * (replacing a previous one); pic_graph_launch replays it on the
+ * context's stream, advancing every run by windows * S steps per launch.
+ * The graph holds kernels only (no memset or copy nodes). */
+pic_status pic_graph_capture(pic_ctx *ctx, int32_t S, int32_t windows);
+pic_status pic_graph_launch(pic_ctx *ctx);
+pic_status pic_graph_release(pic_ctx *ctx);
+
+/* Counters of one run (synchronises the stream). */
+pic_status pic_run_counters(pic_ctx *ctx, int32_t run, pic_counters *cnt);
+
+/* ------------------------------------------------------------------ */
+/* Launch shape.  None of these knobs changes a result: every kernel    */
+/* gives each particle the same arithmetic whichever lane runs it.      */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int32_t waves_per_group; /* wavefront kernels: 1, 2 or 4 wavefronts
+                                (64-particle groups) per workgroup */
+    int32_t tile;            /* compaction kernel: particles per tile,
+                                128, 256 or 512 */
+    int32_t binning;         /* PIC_BIN_NONE (wavefront kernels) or
+                                PIC_BIN_BALLOT (compaction kernel, FP64) */
+    int32_t sort_sub;        /* position bins per cell of the load-time
+                                sort, 1..256 (next pic_particles_set) */
+} pic_tune;
+
+pic_status pic_tune_set(pic_ctx *ctx, const pic_tune *t);
+pic_status pic_tune_get(const pic_ctx *ctx, pic_tune *t);
+
+/* Time `reps` device-driven windows of `steps` steps for each candidate
+ * launch shape (1, 2, 4 wavefronts per workgroup; compaction tiles of
+ * 128, 256, 512 with PIC_FP64), restoring the state after every trial,
+ * and keep the fastest.  Requires sources on all runs. */
+pic_status pic_autotune(pic_ctx *ctx, int32_t steps, int32_t reps,
+                        pic_tune *best, double *ms_best);
+
+/* Number of 64-slot particle groups and the order in which the wavefront
+ * kernels start them: order[i] is the group started i-th (a permutation;
+ * NULL restores slot order).  Groups are runs' slots in position order,
+ * 64 at a time; a predictor of the sub-cycling load can put heavy groups
+ * first. */
+int32_t pic_group_count(const pic_ctx *ctx);
+pic_status pic_order_set(pic_ctx *ctx, const int32_t *order, pic_mem mem);
 
 #ifdef __cplusplus
 }

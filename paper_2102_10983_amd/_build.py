@@ -19,6 +19,7 @@ HIPCC_FLAGS = [
     "-ffp-contract=off", "-fno-fast-math",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I" + os.path.join(ROOT, "include"),
+    "-I" + os.path.join(PKG, "csrc"),
 ]
 
 

@@ -1,0 +1,289 @@
+// common.hpp -- device data layout and helpers shared by the push kernels.
+//
+// A context is a batch of runs.  Each run has its own grid, time step,
+// field ring and particles; its particles occupy a contiguous range of
+// slots, padded to RUN_ALIGN so that no 64-slot group (wavefront kernels)
+// or tile (compaction kernel) straddles two runs.  Padding slots carry
+// perm = -1 and status LOST and are never written back to the caller.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cstdint>
+
+#include "picsub.h"
+
+namespace picsub {
+
+constexpr int NCNT = PIC_KHIST + 2;   // steps_by_k[16], clamps, lost
+constexpr int CNT_CLAMPS = PIC_KHIST;
+constexpr int CNT_LOST = PIC_KHIST + 1;
+constexpr int NSLOT = 256;            // counter slots per run
+constexpr int RUN_ALIGN = 512;        // slot ranges of runs are padded to this
+constexpr int WWIN = 64;              // staged nodes per level in a wavefront window
+constexpr int64_t NO_LEVEL = INT64_MIN;
+
+// Per-run parameters and state, read by the kernels once per wavefront.
+struct RunDesc {
+    const double *ringE, *ringB;      // [D][ncells]
+    const double *table;              // phase table of the on-device sampler
+    double x_origin, dx, dt, qm, psi_max, dtdx;
+    int64_t p_off;                    // first slot of the run
+    int64_t np;                       // particles of the run (slots p_off .. p_off+np-1)
+    int64_t n_cur;                    // current level in device-driven mode
+    int64_t n_stop;                   // device-driven mode: no step starts at or past this level
+    int64_t M, aE, bE, cE, aB, bB, cB;
+    int32_t D, ncells, kmax, margin;
+};
+
+struct PushArgs {
+    const RunDesc *runs;
+    const int32_t *group_run;         // run of each 64-slot group
+    const int32_t *group_order;       // dispatch position -> group
+    double *x, *px, *py, *pz;
+    int8_t *kold;
+    uint8_t *status;
+    const int32_t *perm;              // slot -> caller index (-1: padding)
+    const double *wtab;
+    int8_t *ktrace;
+    uint64_t *cnt;                    // [nruns][NSLOT][NCNT]
+    int64_t kt_n0, kt_first, kt_count;
+    int64_t n0;                       // NO_LEVEL: every run starts at its n_cur
+    int32_t kt_steps, S, ngroups;
+};
+
+__host__ __device__ inline int64_t mod_floor(int64_t a, int64_t m)
+{
+    const int64_t r = a % m;
+    return r < 0 ? r + m : r;
+}
+
+constexpr int64_t wtab_entries(int kmax)
+{
+    return ((int64_t(1) << (2 * (kmax + 1))) - 1) / 3;   // sum_{k<=kmax} 4^k
+}
+
+__host__ __device__ inline int64_t wtab_offset(int k)
+{
+    return ((int64_t(1) << (2 * k)) - 1) / 3;
+}
+
+// Element offsets in the ring of the P+1 levels n-P .. n used at step n.
+template <int P>
+struct Levels {
+    int32_t off[P + 1];
+    __device__ __forceinline__ void at(int32_t slot0, int st, int32_t D, int32_t ncells)
+    {
+#pragma unroll
+        for (int j = 0; j <= P; ++j) {
+            int s = slot0 + st + j;       // < 2 D since S + P <= D
+            s = s >= D ? s - D : s;
+            s = s >= D ? s - D : s;
+            off[j] = s * ncells;
+        }
+    }
+};
+
+// Temporal interpolation at node i, levels ascending (Eqs. (lagrange1-2),
+// (lagrange1-3)): sum_j L_j F_j[i].
+template <int P, typename T, typename W>
+__device__ __forceinline__ double node_comb(const T *__restrict__ f, const int32_t (&off)[P + 1],
+                                            int i, const W &L)
+{
+    double v = L[0] * f[off[0] + i];
+#pragma unroll
+    for (int j = 1; j <= P; ++j) v = v + L[j] * f[off[j] + i];
+    return v;
+}
+
+// Boris momentum update (Sec. III, Eqs. (p)..(gamman)), E along y, B
+// along z, IEEE division and square root, equation order.
+__device__ __forceinline__ void boris(double qm, double dtp, double E, double B, double &px,
+                                      double &py, double &pz)
+{
+    const double c = 0.5 * qm * dtp;
+    const double h = c * E;
+    const double mx = px, my = py + h, mz = pz;
+    const double g = sqrt(1.0 + ((mx * mx + my * my) + mz * mz));
+    const double t = (c * B) / g;
+    const double sz = (2.0 * t) / (1.0 + t * t);
+    const double ax = mx + my * t;
+    const double ay = my - mx * t;
+    px = mx + ay * sz;
+    py = (my - ax * sz) + h;
+    pz = mz;
+}
+
+// 1 / b: hardware estimate refined by two Newton steps
+__device__ __forceinline__ double rcp_nr(double b)
+{
+    double r = __builtin_amdgcn_rcp(b);
+    double e = fma(-b, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-b, r, 1.0);
+    return fma(r, e, r);
+}
+
+// 1 / sqrt(a) for a >= 1: hardware estimate refined by two Newton steps
+__device__ __forceinline__ double rsq_nr(double a)
+{
+    double y = __builtin_amdgcn_rsq(a);
+    const double h = 0.5 * a;
+    double r = fma(-h * y, y, 0.5);
+    y = fma(y, r, y);
+    r = fma(-h * y, y, 0.5);
+    return fma(y, r, y);
+}
+
+// The same Boris update with the refined estimates in place of the IEEE
+// division and square root.
+__device__ __forceinline__ void boris_fast(double qm, double dtp, double E, double B, double &px,
+                                           double &py, double &pz)
+{
+    const double c = 0.5 * qm * dtp;
+    const double h = c * E;
+    const double mx = px, my = py + h, mz = pz;
+    const double ig = rsq_nr(1.0 + ((mx * mx + my * my) + mz * mz));
+    const double t = (c * B) * ig;
+    const double sz = (2.0 * t) * rcp_nr(1.0 + t * t);
+    const double ax = mx + my * t;
+    const double ay = my - mx * t;
+    px = mx + ay * sz;
+    py = (my - ax * sz) + h;
+    pz = mz;
+}
+
+__device__ __forceinline__ void two_sum(float a, float b, float &s, float &e)
+{
+    s = a + b;
+    const float bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+// (hi, lo) += d
+__device__ __forceinline__ void comp_add(float &hi, float &lo, float d)
+{
+    const float y = d + lo;
+    float s, e;
+    two_sum(hi, y, s, e);
+    hi = s;
+    lo = e;
+}
+
+__device__ __forceinline__ void split(double v, float &hi, float &lo)
+{
+    hi = float(v);
+    lo = float(v - double(hi));
+}
+
+__device__ __forceinline__ int wave_min(int v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = min(v, __shfl_xor(v, o));
+    return v;
+}
+
+__device__ __forceinline__ int wave_max(int v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o));
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// Orders this wavefront's LDS writes before its later LDS reads from other
+// lanes (and the reverse); no other wavefront is involved.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Completed steps per k, clamps and lost particles of one lane.
+struct Counts {
+    uint32_t steps[PIC_K_MAX_LIMIT + 1];
+    uint32_t clamps, lost;
+    __device__ __forceinline__ void zero()
+    {
+#pragma unroll
+        for (int k = 0; k <= PIC_K_MAX_LIMIT; ++k) steps[k] = 0;
+        clamps = lost = 0;
+    }
+    __device__ __forceinline__ void step_done(int k)
+    {
+#pragma unroll
+        for (int kk = 0; kk <= PIC_K_MAX_LIMIT; ++kk) steps[kk] += (k == kk);
+    }
+};
+
+// Counters of a whole wavefront, kept wave-uniform (scalar registers):
+// every update is a ballot over the lanes at a point all lanes reach.
+struct WaveCounts {
+    uint32_t steps[PIC_K_MAX_LIMIT + 1];
+    uint32_t clamps, lost;
+    __device__ __forceinline__ void zero()
+    {
+#pragma unroll
+        for (int k = 0; k <= PIC_K_MAX_LIMIT; ++k) steps[k] = 0;
+        clamps = lost = 0;
+    }
+    // lanes with `done` completed a step with exponent k
+    __device__ __forceinline__ void steps_done(bool done, int k)
+    {
+        steps[0] += __popcll(__ballot(done && k == 0));
+        if (__any(done && k > 0)) {
+#pragma unroll
+            for (int kk = 1; kk <= PIC_K_MAX_LIMIT; ++kk)
+                steps[kk] += __popcll(__ballot(done && k == kk));
+        }
+    }
+    __device__ __forceinline__ void flush(uint64_t *__restrict__ slot, int lane) const
+    {
+        if (lane != 0) return;
+#pragma unroll
+        for (int k = 0; k <= PIC_K_MAX_LIMIT; ++k)
+            if (steps[k]) atomicAdd(reinterpret_cast<unsigned long long *>(slot + k), steps[k]);
+        if (clamps) atomicAdd(reinterpret_cast<unsigned long long *>(slot + CNT_CLAMPS), clamps);
+        if (lost) atomicAdd(reinterpret_cast<unsigned long long *>(slot + CNT_LOST), lost);
+    }
+};
+
+// Wavefront reduction, then lane 0 adds into a counter slot.
+__device__ __forceinline__ void flush_wave(Counts &c, uint64_t *__restrict__ slot, int lane)
+{
+#pragma unroll
+    for (int k = 0; k <= PIC_K_MAX_LIMIT; ++k) {
+        const uint32_t v = wave_sum(c.steps[k]);
+        if (lane == 0 && v) atomicAdd(reinterpret_cast<unsigned long long *>(slot + k), v);
+    }
+    const uint32_t cl = wave_sum(c.clamps), lo = wave_sum(c.lost);
+    if (lane == 0 && cl)
+        atomicAdd(reinterpret_cast<unsigned long long *>(slot + CNT_CLAMPS), cl);
+    if (lane == 0 && lo) atomicAdd(reinterpret_cast<unsigned long long *>(slot + CNT_LOST), lo);
+}
+
+// Steps this run takes in a launch of S steps starting at n0.
+__device__ __forceinline__ int run_steps(const PushArgs &a, const RunDesc &R, int64_t n0)
+{
+    if (a.n0 != NO_LEVEL) return a.S;                 // host-driven launch
+    const int64_t left = R.n_stop - n0;
+    return left <= 0 ? 0 : (left < a.S ? int(left) : a.S);
+}
+
+__device__ __forceinline__ void ktrace_put(const PushArgs &a, int64_t kt_u, int64_t n, int8_t v)
+{
+    if (kt_u >= 0) {
+        const int64_t r = n - a.kt_n0;
+        if (r >= 0 && r < a.kt_steps) a.ktrace[r * a.kt_count + kt_u] = v;
+    }
+}
+
+}  // namespace picsub

@@ -26,7 +26,11 @@ MEM_HOST, MEM_DEVICE = 0, 1
 # every symbol the header declares
 EXPORTS = ("pic_create", "pic_destroy", "pic_last_error", "pic_particles_set",
            "pic_fields_load", "pic_fields_load_lattice", "pic_push_subcycled",
-           "pic_ktrace_set", "pic_diag", "pic_counters_reset", "pic_tune_set")
+           "pic_ktrace_set", "pic_diag", "pic_counters_reset", "pic_batch_create",
+           "pic_fields_load_r", "pic_fields_load_lattice_r", "pic_source_set", "pic_advance",
+           "pic_run_level", "pic_graph_capture", "pic_graph_launch", "pic_graph_release",
+           "pic_run_counters", "pic_tune_set", "pic_tune_get", "pic_autotune",
+           "pic_group_count", "pic_order_set")
 
 
 class PicError(RuntimeError):
@@ -55,6 +59,16 @@ class Counters(C.Structure):
                 "sub_steps_by_k": list(self.sub_steps_by_k)}
 
 
+class Tune(C.Structure):
+    _fields_ = [("waves_per_group", C.c_int32), ("tile", C.c_int32), ("binning", C.c_int32),
+                ("sort_sub", C.c_int32)]
+
+    def as_dict(self):
+        return {"waves_per_group": self.waves_per_group, "tile": self.tile,
+                "binning": {v: k for k, v in BINNING.items()}[self.binning],
+                "sort_sub": self.sort_sub}
+
+
 _lib = None
 
 
@@ -80,7 +94,22 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "pic_ktrace_set": ([vp, vp, i64, i32, i64, i64], C.c_int),
         "pic_diag": ([vp, C.c_int, vp, vp, vp, vp, vp, vp, vp, C.POINTER(Counters)], C.c_int),
         "pic_counters_reset": ([vp], C.c_int),
-        "pic_tune_set": ([vp, i32, i32], C.c_int),
+        "pic_batch_create": ([vp, vp, i32, vp, C.POINTER(vp)], C.c_int),
+        "pic_fields_load_r": ([vp, i32, i64, C.c_int, vp, vp], C.c_int),
+        "pic_fields_load_lattice_r": ([vp, i32, i64, i32, vp, i64, i64, i64, i64, i64, i64,
+                                       i64], C.c_int),
+        "pic_source_set": ([vp, i32, i64, i64, vp, i64, i64, i64, i64, i64, i64, i64], C.c_int),
+        "pic_advance": ([vp, i32], C.c_int),
+        "pic_run_level": ([vp, i32, C.POINTER(i64)], C.c_int),
+        "pic_graph_capture": ([vp, i32, i32], C.c_int),
+        "pic_graph_launch": ([vp], C.c_int),
+        "pic_graph_release": ([vp], C.c_int),
+        "pic_run_counters": ([vp, i32, C.POINTER(Counters)], C.c_int),
+        "pic_tune_set": ([vp, C.POINTER(Tune)], C.c_int),
+        "pic_tune_get": ([vp, C.POINTER(Tune)], C.c_int),
+        "pic_autotune": ([vp, i32, i32, C.POINTER(Tune), C.POINTER(dbl)], C.c_int),
+        "pic_group_count": ([vp], i32),
+        "pic_order_set": ([vp, vp, C.c_int], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -109,25 +138,41 @@ def _dev_ptr(t, dtype, n=None):
     return t.data_ptr()
 
 
-class Pusher:
-    """One context of the C ABI: np particles, a field ring, a stream."""
+def make_params(*, ncells: int, order: int, dx: float, dt: float, psi_max: float,
+                x_origin: float = 0.0, qm: float = -1.0, k_max: int = 8,
+                ring_depth: int | None = None, precision: str = "fp64",
+                binning: str = "none") -> Params:
+    return Params(ncells=ncells, order=order, ring_depth=int(ring_depth or (order + 1)),
+                  k_max=k_max, precision=PRECISION[precision], binning=BINNING[binning],
+                  x_origin=x_origin, dx=dx, dt=dt, qm=qm, psi_max=psi_max)
 
-    def __init__(self, *, num: int, ncells: int, order: int, dx: float, dt: float,
-                 psi_max: float, x_origin: float = 0.0, qm: float = -1.0, k_max: int = 8,
-                 ring_depth: int | None = None, precision: str = "fp64",
-                 binning: str = "none", stream=None):
+
+class Pusher:
+    """One context of the C ABI: a batch of runs (one run by default), each
+    with its particles and field ring, on one stream.
+
+    Pusher(num=..., ncells=..., ...) builds a one-run context;
+    Pusher(runs=[(num, Params), ...]) a batch."""
+
+    def __init__(self, *, num: int | None = None, runs=None, stream=None, **kw):
         torch = _torch()
         self._lib = load_library()
-        self.num = int(num)
-        self.order = int(order)
-        self.ring_depth = int(ring_depth or (order + 1))
-        self.prm = Params(ncells=ncells, order=order, ring_depth=self.ring_depth, k_max=k_max,
-                          precision=PRECISION[precision], binning=BINNING[binning],
-                          x_origin=x_origin, dx=dx, dt=dt, qm=qm, psi_max=psi_max)
+        if runs is None:
+            runs = [(int(num), make_params(**kw))]
+        self.nruns = len(runs)
+        self.nums = [int(n) for n, _ in runs]
+        self.num = sum(self.nums)
+        self.offsets = np.concatenate([[0], np.cumsum(self.nums)]).astype(np.int64)
+        self.params = [p for _, p in runs]
+        self.prm = self.params[0]
+        self.order = int(self.prm.order)
+        self.ring_depth = int(self.prm.ring_depth)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
+        arr = (Params * self.nruns)(*self.params)
+        counts = (C.c_int64 * self.nruns)(*self.nums)
         self._ctx = C.c_void_p()
-        st = self._lib.pic_create(C.byref(self.prm), self.num, C.c_void_p(self.stream.cuda_stream),
-                                  C.byref(self._ctx))
+        st = self._lib.pic_batch_create(arr, counts, self.nruns,
+                                        C.c_void_p(self.stream.cuda_stream), C.byref(self._ctx))
         if st != 0:
             msg = self._err()
             if self._ctx:
@@ -135,6 +180,7 @@ class Pusher:
                 self._ctx = C.c_void_p()
             raise PicError(st, msg)
         self._keep = []
+        self._sources = {}
 
     # -- helpers ---------------------------------------------------------
     def _err(self) -> str:
@@ -200,8 +246,90 @@ class Pusher:
         self._check(self._lib.pic_fields_load_lattice(self._ctx, n_first, count, tp, M,
                                                       *[int(c) for c in coeffs]))
 
+    def fields_load_r(self, run: int, n: int, Ey, Bz):
+        E = np.ascontiguousarray(Ey, dtype=np.float64)
+        B = np.ascontiguousarray(Bz, dtype=np.float64)
+        if E.size != self.params[run].ncells or B.size != self.params[run].ncells:
+            raise ValueError("wrong field length")
+        self._check(self._lib.pic_fields_load_r(self._ctx, run, n, MEM_HOST, E.ctypes.data,
+                                                B.ctypes.data))
+
+    def fields_load_lattice_r(self, run: int, n_first: int, count: int, table, M: int, coeffs):
+        torch = _torch()
+        tp = _dev_ptr(table, torch.float64)
+        self._check(self._lib.pic_fields_load_lattice_r(self._ctx, run, n_first, count, tp, M,
+                                                        *[int(c) for c in coeffs]))
+
     def push(self, n: int, S: int = 1):
         self._check(self._lib.pic_push_subcycled(self._ctx, n, S))
+
+    # -- device-driven mode ------------------------------------------------
+    def source_set(self, run: int, n_start: int, table, M: int, coeffs, n_stop=None):
+        """Attach a device phase table to a run at level n_start, stopping at
+        n_stop (the tensor is kept alive by this object)."""
+        torch = _torch()
+        tp = _dev_ptr(table, torch.float64)
+        if table.numel() < M:
+            raise ValueError("table shorter than M")
+        self._sources[run] = table
+        stop = (1 << 63) - 1 if n_stop is None else int(n_stop)
+        self._check(self._lib.pic_source_set(self._ctx, run, n_start, stop, tp, M,
+                                             *[int(c) for c in coeffs]))
+
+    def advance(self, S: int):
+        self._check(self._lib.pic_advance(self._ctx, S))
+
+    def run_level(self, run: int = 0) -> int:
+        n = C.c_int64()
+        self._check(self._lib.pic_run_level(self._ctx, run, C.byref(n)))
+        return n.value
+
+    def graph_capture(self, S: int, windows: int):
+        self._check(self._lib.pic_graph_capture(self._ctx, S, windows))
+
+    def graph_launch(self):
+        self._check(self._lib.pic_graph_launch(self._ctx))
+
+    def graph_release(self):
+        self._check(self._lib.pic_graph_release(self._ctx))
+
+    def run_counters(self, run: int) -> dict:
+        c = Counters()
+        self._check(self._lib.pic_run_counters(self._ctx, run, C.byref(c)))
+        return c.as_dict()
+
+    # -- launch shape --------------------------------------------------------
+    def tune_get(self) -> dict:
+        t = Tune()
+        self._check(self._lib.pic_tune_get(self._ctx, C.byref(t)))
+        return t.as_dict()
+
+    def tune_set(self, waves_per_group=None, tile=None, binning=None, sort_sub=None):
+        cur = self.tune_get()
+        t = Tune(waves_per_group=waves_per_group or cur["waves_per_group"],
+                 tile=tile or cur["tile"], binning=BINNING[binning or cur["binning"]],
+                 sort_sub=sort_sub or cur["sort_sub"])
+        self._check(self._lib.pic_tune_set(self._ctx, C.byref(t)))
+
+    def autotune(self, steps: int, reps: int = 1):
+        t = Tune()
+        ms = C.c_double()
+        self._check(self._lib.pic_autotune(self._ctx, steps, reps, C.byref(t), C.byref(ms)))
+        return t.as_dict(), ms.value
+
+    def group_count(self) -> int:
+        return int(self._lib.pic_group_count(self._ctx))
+
+    def order_set(self, order):
+        """Dispatch order of the 64-slot groups (host int32 permutation, or
+        None for slot order)."""
+        if order is None:
+            self._check(self._lib.pic_order_set(self._ctx, None, MEM_HOST))
+            return
+        o = np.ascontiguousarray(order, dtype=np.int32)
+        if o.size != self.group_count():
+            raise ValueError("order must list every group once")
+        self._check(self._lib.pic_order_set(self._ctx, o.ctypes.data, MEM_HOST))
 
     def ktrace_set(self, buf, n_first: int = 0, first: int = 0):
         """Record k for caller indices [first, first + buf.shape[1]) at steps
@@ -218,9 +346,6 @@ class Pusher:
 
     def counters_reset(self):
         self._check(self._lib.pic_counters_reset(self._ctx))
-
-    def tune(self, block: int = 0, tile: int = 0):
-        self._check(self._lib.pic_tune_set(self._ctx, block, tile))
 
     def counters(self) -> dict:
         c = Counters()

@@ -55,3 +55,60 @@ class DeviceRun:
 
     def close(self):
         self.pusher.close()
+
+
+class BatchRun:
+    """Many workloads in one context, advanced by device-driven windows of S
+    steps (each run stops at its own step count); optionally captured into a
+    HIP graph that replays a whole pass."""
+
+    def __init__(self, wls, *, S: int = 250, precision: str = "fp64fast",
+                 binning: str = "none", k_max: int = 8, stream=None):
+        import torch
+        self.torch = torch
+        self.wls = list(wls)
+        self.S = int(S)
+        order = self.wls[0].order
+        runs = []
+        self.tables = []
+        for wl in self.wls:
+            assert wl.order == order
+            runs.append((wl.num, picsub.make_params(
+                ncells=wl.ncells, order=order, dx=wl.dx, dt=wl.dt, psi_max=wl.psi_max,
+                x_origin=wl.x_origin, k_max=k_max, ring_depth=self.S + order,
+                precision=precision, binning=binning)))
+            table, M, shift = wl.table()
+            self.tables.append((torch.from_numpy(np.ascontiguousarray(table)).to("cuda"), int(M),
+                                W.shifted_coeffs(wl.lat, shift)))
+        self.pusher = picsub.Pusher(runs=runs, stream=stream)
+        self.x0 = torch.from_numpy(np.concatenate([wl.x0 for wl in self.wls])).to("cuda")
+        self.p0 = [torch.from_numpy(np.concatenate([wl.p0[c] for wl in self.wls])).to("cuda")
+                   for c in range(3)]
+        self.max_steps = max(wl.steps for wl in self.wls)
+        self.windows = (self.max_steps + self.S - 1) // self.S
+
+    @property
+    def sub_steps_hint(self):
+        return None
+
+    def reset(self):
+        self.pusher.particles_set(self.x0, *self.p0)
+        for r, (wl, (tab, M, co)) in enumerate(zip(self.wls, self.tables)):
+            self.pusher.source_set(r, 0, tab, M, co, n_stop=wl.steps)
+
+    def run_all(self):
+        """One full pass: every run to its own last step (asynchronous)."""
+        for _ in range(self.windows):
+            self.pusher.advance(self.S)
+
+    def capture(self):
+        self.pusher.graph_capture(self.S, self.windows)
+
+    def replay(self):
+        self.pusher.graph_launch()
+
+    def diag(self):
+        return self.pusher.diag()
+
+    def close(self):
+        self.pusher.close()

@@ -221,3 +221,28 @@ def stress_case(psi_max: float = 0.01, num: int = 1 << 24, periods: float = 100.
     65536 cells, 3rd order."""
     return make_workload(f"stress psi={psi_max:g} P={num}", num, 150.0, 75, 65536,
                          periods, 3, psi_max, 200.0, seed=5, theta=10.0 / 511.0)
+
+
+def batch_case(seed: int = 3, nruns: int = 64, periods: float = 50.0,
+               p_range=(1e3, 4e6), a0_range=(1.0, 150.0), n_t_choices=(40, 75, 150),
+               cells_range=(2048, 16384), span_lambda: float = 1.0, scale: float = 1.0):
+    """Independent runs of uneven size: particle counts log-uniform in p_range
+    (times `scale`), a0 log-uniform in a0_range, T/dt drawn from
+    n_t_choices, grids log-uniform in cells_range and enlarged where the run
+    needs more room (x0 span + periods wavelengths + margins), electrons at
+    rest over `span_lambda` wavelengths, 3rd order, psi_max = 0.01."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    runs = []
+    for r in range(nruns):
+        num = max(1, int(round(scale * math.exp(rng.uniform(math.log(p_range[0]),
+                                                            math.log(p_range[1]))))))
+        a0 = math.exp(rng.uniform(math.log(a0_range[0]), math.log(a0_range[1])))
+        n_t = int(n_t_choices[int(rng.integers(0, len(n_t_choices)))])
+        cells = int(round(math.exp(rng.uniform(math.log(cells_range[0]),
+                                               math.log(cells_range[1])))))
+        need = int(math.ceil((span_lambda + periods + 0.5) * n_t * 100 / 101)) + 16
+        cells = max(cells, need)
+        wl = make_workload(f"run{r} a0={a0:.3g} T/dt={n_t}", num, a0, n_t, cells, periods,
+                           3, 0.01, span_lambda, seed=1000 * seed + r)
+        runs.append(wl)
+    return runs

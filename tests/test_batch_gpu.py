@@ -1,0 +1,157 @@
+"""GPU tests of batches of uneven runs, device-driven windows, captured
+graphs, the autotuner and the group dispatch order.
+
+None of these may change a result: every run of a batch must equal the
+same run pushed alone and the FP64 oracle, bit for bit in PIC_FP64.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2102_10983_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _small_batch(seed=7, nruns=5, precision="fp64"):
+    """Runs of different size, a0, dt and grid; one empty run."""
+    runs = W.batch_case(seed=seed, nruns=nruns, periods=3.0, p_range=(50, 3000),
+                        a0_range=(5.0, 150.0), cells_range=(400, 900))
+    runs[2] = W.make_workload("empty", 0, 20.0, 40, 300, 3.0, 3, 0.01, 1.0, seed=99)
+    return runs
+
+
+def _state(d):
+    return {k: d[k].copy() for k in ("x", "px", "py", "pz", "k_last", "status")}
+
+
+def _same(a, b):
+    return all(np.array_equal(a[k], b[k]) for k in a)
+
+
+def test_batch_equals_single_runs_and_oracle(torch_gpu):
+    from paper_2102_10983_amd import runner
+    from parity import compare
+    wls = _small_batch()
+    br = runner.BatchRun(wls, S=37, precision="fp64")
+    br.reset()
+    br.run_all()
+    d = br.diag()
+    per_run = [br.pusher.run_counters(r) for r in range(len(wls))]
+    offs = br.pusher.offsets
+    br.close()
+    for r, wl in enumerate(wls):
+        _say(f"run {r}: {wl.name} num={wl.num} steps={wl.steps}")
+        sl = slice(offs[r], offs[r + 1])
+        if wl.num == 0:
+            assert per_run[r]["steps"] == 0
+            continue
+        one = runner.DeviceRun(wl, S=wl.steps, binning="none", precision="fp64")
+        one.reset()
+        one.advance(wl.steps)
+        d1 = one.diag()
+        one.close()
+        for k in ("x", "px", "py", "pz", "k_last", "status"):
+            assert np.array_equal(d[k][sl], d1[k]), (r, k)
+        sub = {k: d[k][sl] for k in ("x", "px", "py", "pz", "status")}
+        res = compare(wl, wl.steps, sub, np.arange(wl.num), 1e-12)
+        assert res["bitwise"] == wl.num
+        c = res["oracle_counters"]
+        assert per_run[r]["steps"] == c.steps and per_run[r]["sub_steps"] == c.sub_steps
+
+
+def test_graph_replays_match_eager(torch_gpu):
+    """A captured pass replayed several times, with eager work between the
+    replays, equals the eager pass every time."""
+    torch = torch_gpu
+    from paper_2102_10983_amd import runner
+    wls = _small_batch(seed=8)
+    eager = runner.BatchRun(wls, S=29, precision="fp64fast")
+    eager.reset()
+    eager.run_all()
+    ref = _state(eager.diag())
+    ref_cnt = eager.pusher.counters()
+    eager.close()
+    g = runner.BatchRun(wls, S=29, precision="fp64fast")
+    g.reset()
+    g.capture()
+    for rep in range(3):
+        g.reset()
+        g.pusher.counters_reset()
+        g.replay()
+        torch.cuda.synchronize()
+        got = g.diag()                         # eager copies between replays
+        _ = torch.ones(1000, device="cuda").sum().item()
+        assert _same(_state(got), ref), rep
+        assert got["counters"] == ref_cnt, rep
+        for r, wl in enumerate(wls):
+            assert g.pusher.run_level(r) >= wl.steps
+    g.pusher.graph_release()
+    g.close()
+
+
+def test_autotune_leaves_no_trace_and_keeps_results(torch_gpu):
+    from paper_2102_10983_amd import runner
+    wls = _small_batch(seed=9)
+    b = runner.BatchRun(wls, S=40, precision="fp64")
+    b.reset()
+    before = _state(b.diag())
+    best, ms = b.pusher.autotune(steps=40, reps=1)
+    _say("autotune", best, ms)
+    after = _state(b.diag())
+    assert _same(before, after)
+    assert b.pusher.counters()["steps"] == 0
+    assert b.pusher.run_level(0) == 0
+    b.run_all()
+    tuned = _state(b.diag())
+    b.close()
+    ref = runner.BatchRun(wls, S=40, precision="fp64")
+    ref.reset()
+    ref.run_all()
+    assert _same(tuned, _state(ref.diag()))
+    ref.close()
+
+
+@pytest.mark.parametrize("tune", [dict(waves_per_group=2), dict(waves_per_group=4),
+                                  dict(binning="ballot", tile=128),
+                                  dict(binning="ballot", tile=512)])
+def test_launch_shapes_and_dispatch_order_change_nothing(torch_gpu, tune):
+    from paper_2102_10983_amd import runner
+    wls = _small_batch(seed=10)
+    ref = runner.BatchRun(wls, S=31, precision="fp64")
+    ref.reset()
+    ref.run_all()
+    want = _state(ref.diag())
+    ref.close()
+    b = runner.BatchRun(wls, S=31, precision="fp64")
+    b.pusher.tune_set(**tune)
+    ng = b.pusher.group_count()
+    b.pusher.order_set(np.random.default_rng(1).permutation(ng).astype(np.int32))
+    b.reset()
+    b.run_all()
+    assert _same(_state(b.diag()), want)
+    b.close()
+
+
+def test_order_must_be_a_permutation(torch_gpu):
+    from paper_2102_10983_amd import picsub, runner
+    b = runner.BatchRun(_small_batch(seed=11), S=10)
+    ng = b.pusher.group_count()
+    with pytest.raises(picsub.PicError):
+        b.pusher.order_set(np.zeros(ng, dtype=np.int32))
+    b.close()
