@@ -270,6 +270,73 @@ pic_status pic_autotune(pic_ctx *ctx, int32_t steps, int32_t reps,
 int32_t pic_group_count(const pic_ctx *ctx);
 pic_status pic_order_set(pic_ctx *ctx, const int32_t *order, pic_mem mem);
 
+/* ------------------------------------------------------------------
+ * Learned load predictor.
+ *
+ * Not part of the paper's method: the paper decides k from Psi alone
+ * (Sec. III) and that decision is kept unchanged.  The predictor only
+ * estimates, one step ahead, how many sub-steps each particle will take,
+ * so that particles of similar load share a wavefront and the heaviest
+ * wavefronts start first and issue at raised priority.  No result of the
+ * push depends on it: a wrong prediction costs time, never accuracy.
+ *
+ * Network: 8 features -> 64 -> 64 -> 1, GELU (erf form) after the two
+ * hidden layers, output = predicted log2 of the sub-steps taken over the
+ * next steps.  Parameter vector (PIC_MLP_NPARAM floats or BF16 words), in
+ * this order: W1[64][8], b1[64], W2[64][64], b2[64], W3[64], b3.
+ * Features are standardised as (f - mean) * inv_std with norm =
+ * {mean[8], inv_std[8]}.  Inference reads BF16 weights (round-to-nearest-even of the FP32
+ * masters) and accumulates in FP32; training keeps FP32 masters and
+ * computes gradients of the BF16-rounded forward (straight-through).
+ * ------------------------------------------------------------------ */
+#define PIC_MLP_FEATURES 8
+#define PIC_MLP_HIDDEN 64
+#define PIC_MLP_NPARAM 4801
+
+/* Features of every particle at level n (n = -2^63: each run's level of
+ * the device-driven mode, pic_run_level), written to feat[caller index *
+ * 8] (device, FP32):
+ *   |E_y| and |B_z| at the particle from level n-1, their backward
+ *   differences with level n-2 divided by dt, gamma, p_x, |p_perp|, and
+ *   log(a0) of the particle's run (run_a0: host array, one per run).
+ * Spatial interpolation is linear, as in the gather.  Particles that are
+ * lost get zeros.  Levels n-1 and n-2 must be in every run's ring
+ * (PIC_E_LEVEL otherwise).  Synchronous. */
+pic_status pic_features(pic_ctx *ctx, int64_t n, const float *run_a0, float *feat);
+
+/* Forward pass over n feature rows (all device pointers, FP32 except the
+ * BF16 weights); out[i] = network(feat[i]).  Enqueued on hip_stream
+ * (NULL: the null stream); returns without synchronising. */
+pic_status pic_mlp_forward(const uint16_t *w_bf16, const float *norm, const float *feat,
+                           float *out, int64_t n, void *hip_stream);
+
+/* Gradient of the mean squared error inv_total * sum_i (out_i - target_i)^2
+ * with respect to the FP32 parameter vector w, accumulated (atomically)
+ * into grad, and the loss into *loss; the caller zeroes both.  The forward
+ * pass inside uses w rounded to BF16.  Several calls over slices of a
+ * data set with the same inv_total = 1/total sum to the full gradient.
+ * Device pointers; enqueued on hip_stream. */
+pic_status pic_mlp_grad(const float *w, const float *norm, const float *feat, const float *target,
+                        int64_t n, float inv_total, float *grad, float *loss, void *hip_stream);
+
+/* One Adam update (Kingma and Ba, bias-corrected, step t >= 1) of n FP32
+ * parameters in place; m and v are the moment buffers (start at zero).
+ * Device pointers; enqueued on hip_stream. */
+pic_status pic_mlp_adam(float *w, float *m, float *v, const float *grad, int32_t n, float lr,
+                        float beta1, float beta2, float eps, int32_t t, void *hip_stream);
+
+/* Re-bin the particles of every run by predicted load: score[caller
+ * index] (device, FP32, larger = more sub-steps; NaN = lightest) is cut
+ * into nbuckets buckets of the given width below the largest score, and
+ * each run's slots are re-filled bucket by bucket (heaviest first), in
+ * position order inside a bucket.  Then the groups are started heaviest
+ * first (by the largest score of their lanes) and the prio_groups
+ * heaviest issue at raised priority.  Particles stay in their run;
+ * results are unchanged.  Not allowed while a graph is captured
+ * (PIC_E_STATE).  Synchronous. */
+pic_status pic_prebin(pic_ctx *ctx, const float *score, int32_t nbuckets, float width,
+                      int32_t prio_groups);
+
 #ifdef __cplusplus
 }
 #endif

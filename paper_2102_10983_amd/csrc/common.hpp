@@ -41,6 +41,7 @@ struct PushArgs {
     const RunDesc *runs;
     const int32_t *group_run;         // run of each 64-slot group
     const int32_t *group_order;       // dispatch position -> group
+    const int8_t *group_prio;         // base issue priority of each group (0 or 1)
     double *x, *px, *py, *pz;
     int8_t *kold;
     uint8_t *status;
@@ -268,6 +269,18 @@ __device__ __forceinline__ void flush_wave(Counts &c, uint64_t *__restrict__ slo
     if (lane == 0 && cl)
         atomicAdd(reinterpret_cast<unsigned long long *>(slot + CNT_CLAMPS), cl);
     if (lane == 0 && lo) atomicAdd(reinterpret_cast<unsigned long long *>(slot + CNT_LOST), lo);
+}
+
+// Issue priority of a wavefront: base (0 or 1) from the group's predicted
+// load, + 2 inside sub-step loops.
+__device__ __forceinline__ void set_prio(int p)
+{
+    switch (p) {
+    case 0: __builtin_amdgcn_s_setprio(0); break;
+    case 1: __builtin_amdgcn_s_setprio(1); break;
+    case 2: __builtin_amdgcn_s_setprio(2); break;
+    default: __builtin_amdgcn_s_setprio(3); break;
+    }
 }
 
 // Steps this run takes in a launch of S steps starting at n0.

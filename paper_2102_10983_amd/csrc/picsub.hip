@@ -36,6 +36,7 @@
 #include "push_tile.hpp"
 #include "push_wave.hpp"
 #include "setup.hpp"
+#include "mlp.hpp"
 
 using namespace picsub;
 
@@ -73,6 +74,7 @@ struct pic_ctx {
     // run table and group maps
     RunDesc *d_runs = nullptr;
     int32_t *group_run = nullptr, *group_order = nullptr;
+    int8_t *group_prio = nullptr;
     int32_t ngroups = 0;
     double *wtab = nullptr;
     uint64_t *cnt = nullptr;
@@ -140,7 +142,7 @@ void free_all(pic_ctx *c)
     c->gexec = nullptr;
     c->graph = nullptr;
     void *ptrs[] = {c->x, c->px, c->py, c->pz, c->kold, c->status, c->perm, c->key,
-                    c->d_runs, c->group_run, c->group_order, c->wtab, c->cnt};
+                    c->d_runs, c->group_run, c->group_order, c->group_prio, c->wtab, c->cnt};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (RunHost &r : c->runs) {
@@ -152,6 +154,7 @@ void free_all(pic_ctx *c)
     c->kold = nullptr;
     c->status = nullptr;
     c->perm = c->key = c->group_run = c->group_order = nullptr;
+    c->group_prio = nullptr;
     c->d_runs = nullptr;
     c->cnt = nullptr;
 }
@@ -245,6 +248,7 @@ PushArgs push_args(pic_ctx *ctx, int64_t n0, int32_t S)
     a.runs = ctx->d_runs;
     a.group_run = ctx->group_run;
     a.group_order = ctx->group_order;
+    a.group_prio = ctx->group_prio;
     a.x = ctx->x;
     a.px = ctx->px;
     a.py = ctx->py;
@@ -437,6 +441,7 @@ pic_status pic_batch_create(const pic_params *per_run, const int64_t *np, int32_
         (st = dev_alloc(ctx, &ctx->d_runs, size_t(nruns))) ||
         (st = dev_alloc(ctx, &ctx->group_run, size_t(ctx->ngroups))) ||
         (st = dev_alloc(ctx, &ctx->group_order, size_t(ctx->ngroups))) ||
+        (st = dev_alloc(ctx, &ctx->group_prio, size_t(ctx->ngroups))) ||
         (st = dev_alloc(ctx, &ctx->wtab, size_t(wtab_entries(ctx->kmax_all)) * 2 * (ctx->order + 1))) ||
         (st = dev_alloc(ctx, &ctx->cnt, cnt_words(ctx)))) {
         free_all(ctx);
@@ -471,6 +476,7 @@ pic_status pic_batch_create(const pic_params *per_run, const int64_t *np, int32_
     HIP_TRY(ctx, hipMemsetAsync(ctx->cnt, 0, cnt_words(ctx) * sizeof(uint64_t), ctx->stream));
     HIP_TRY(ctx, hipMemsetAsync(ctx->status, PIC_PARTICLE_LOST, n, ctx->stream));
     HIP_TRY(ctx, hipMemsetAsync(ctx->perm, 0xFF, n * sizeof(int32_t), ctx->stream));
+    HIP_TRY(ctx, hipMemsetAsync(ctx->group_prio, 0, size_t(ctx->ngroups), ctx->stream));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     return PIC_OK;
 }
@@ -567,6 +573,15 @@ pic_status pic_particles_set(pic_ctx *ctx, pic_mem mem, const double *x, const d
     }
     if (e == hipSuccess)
         e = hipMemsetAsync(ctx->cnt, 0, cnt_words(ctx) * sizeof(uint64_t), ctx->stream);
+    if (e == hipSuccess)
+        e = hipMemsetAsync(ctx->group_prio, 0, size_t(ctx->ngroups), ctx->stream);
+    if (e == hipSuccess) {
+        std::vector<int32_t> id(size_t(ctx->ngroups));
+        std::iota(id.begin(), id.end(), 0);
+        e = hipMemcpyAsync(ctx->group_order, id.data(), id.size() * 4, hipMemcpyHostToDevice,
+                           ctx->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) result = fail(ctx, PIC_E_DEVICE, "particle load: %s", hipGetErrorString(e));
     else ctx->have_particles = true;
@@ -867,6 +882,7 @@ pic_status pic_order_set(pic_ctx *ctx, const int32_t *order, pic_mem mem)
         std::iota(id.begin(), id.end(), 0);
         HIP_TRY(ctx, hipMemcpyAsync(ctx->group_order, id.data(), bytes, hipMemcpyHostToDevice,
                                     ctx->stream));
+        HIP_TRY(ctx, hipMemsetAsync(ctx->group_prio, 0, size_t(ctx->ngroups), ctx->stream));
         HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
         return PIC_OK;
     }
@@ -990,6 +1006,196 @@ pic_status pic_autotune(pic_ctx *ctx, int32_t steps, int32_t reps, pic_tune *bes
     if (best) *best = winner;
     if (ms_best) *ms_best = wbest;
     return PIC_OK;
+}
+
+
+// ---------------------------------------------------------------------
+// Load predictor
+// ---------------------------------------------------------------------
+pic_status pic_mlp_forward(const uint16_t *w_bf16, const float *norm, const float *feat,
+                           float *out, int64_t n, void *hip_stream)
+{
+    if (!w_bf16 || !norm || (n > 0 && (!feat || !out)) || n < 0) return PIC_E_ARG;
+    if (n == 0) return PIC_OK;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    mlp_forward_kernel<<<grid_for(n, 256, 8192), 256, 0, s>>>(w_bf16, norm, feat, out, n);
+    return hipGetLastError() == hipSuccess ? PIC_OK : PIC_E_DEVICE;
+}
+
+pic_status pic_mlp_grad(const float *w, const float *norm, const float *feat, const float *target,
+                        int64_t n, float inv_total, float *grad, float *loss, void *hip_stream)
+{
+    if (!w || !norm || !grad || !loss || n < 0 || (n > 0 && (!feat || !target))) return PIC_E_ARG;
+    if (n == 0) return PIC_OK;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    mlp_grad_kernel<<<grid_for(n, 64, 2048), 64, 0, s>>>(w, norm, feat, target, n, inv_total, grad,
+                                                         loss);
+    return hipGetLastError() == hipSuccess ? PIC_OK : PIC_E_DEVICE;
+}
+
+pic_status pic_mlp_adam(float *w, float *m, float *v, const float *grad, int32_t n, float lr,
+                        float beta1, float beta2, float eps, int32_t t, void *hip_stream)
+{
+    if (!w || !m || !v || !grad || n < 0 || t < 1) return PIC_E_ARG;
+    if (n == 0) return PIC_OK;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const float c1 = 1.f / (1.f - std::pow(beta1, float(t)));
+    const float c2 = 1.f / (1.f - std::pow(beta2, float(t)));
+    adam_kernel<<<(n + 255) / 256, 256, 0, s>>>(w, m, v, grad, n, lr, beta1, beta2, eps, c1, c2);
+    return hipGetLastError() == hipSuccess ? PIC_OK : PIC_E_DEVICE;
+}
+
+pic_status pic_features(pic_ctx *ctx, int64_t n, const float *run_a0, float *feat)
+{
+    CTX_CHECK(ctx);
+    if (!run_a0 || (!feat && ctx->np > 0)) return fail(ctx, PIC_E_ARG, "null features or a0");
+    if (!ctx->have_particles) return fail(ctx, PIC_E_STATE, "particles not loaded");
+    for (int r = 0; r < ctx->nruns; ++r) {
+        const RunHost &R = ctx->runs[size_t(r)];
+        const int64_t lev = n != NO_LEVEL ? n : R.n_dev;
+        for (int64_t m = lev - 2; m <= lev - 1; ++m)
+            if (R.tags[size_t(mod_floor(m, R.prm.ring_depth))] != m)
+                return fail(ctx, PIC_E_LEVEL, "run %d: level %lld is not in the ring", r,
+                            (long long)m);
+        if (!(run_a0[r] > 0)) return fail(ctx, PIC_E_ARG, "run %d: a0 must be > 0", r);
+    }
+    if (ctx->np == 0) return PIC_OK;
+    float *da0 = nullptr;
+    pic_status st = dev_alloc(ctx, &da0, size_t(ctx->nruns));
+    if (st) return st;
+    hipError_t e = hipMemcpyAsync(da0, run_a0, size_t(ctx->nruns) * 4, hipMemcpyHostToDevice,
+                                  ctx->stream);
+    if (e == hipSuccess) {
+        FeatArgs f{ctx->d_runs, ctx->group_run, ctx->x, ctx->px, ctx->py, ctx->pz, ctx->status,
+                   ctx->perm, da0, feat, n, ctx->slots};
+        features_kernel<<<grid_for(ctx->slots, 256, 8192), 256, 0, ctx->stream>>>(f);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    (void)hipFree(da0);
+    if (e != hipSuccess) return fail(ctx, PIC_E_DEVICE, "features: %s", hipGetErrorString(e));
+    return PIC_OK;
+}
+
+pic_status pic_prebin(pic_ctx *ctx, const float *score, int32_t nbuckets, float width,
+                      int32_t prio_groups)
+{
+    CTX_CHECK(ctx);
+    if (!ctx->have_particles) return fail(ctx, PIC_E_STATE, "particles not loaded");
+    if (!score && ctx->np > 0) return fail(ctx, PIC_E_ARG, "null score");
+    if (nbuckets < 1 || nbuckets > 64 || !(width > 0) || prio_groups < 0)
+        return fail(ctx, PIC_E_ARG, "need 1..64 buckets, width > 0, prio_groups >= 0");
+    if (ctx->gexec) return fail(ctx, PIC_E_STATE, "release the captured graph before re-binning");
+    if (ctx->np == 0) return PIC_OK;
+    const int64_t slots = ctx->slots;
+    const size_t n = size_t(slots);
+    const int psub = 4;      // position bins per cell inside a bucket
+    // key space: run-major, then bucket, then position
+    std::vector<int64_t> bin_off(size_t(ctx->nruns)), shift(size_t(ctx->nruns));
+    int64_t nb = 0;
+    for (int r = 0; r < ctx->nruns; ++r) {
+        const RunHost &R = ctx->runs[size_t(r)];
+        bin_off[size_t(r)] = nb;
+        shift[size_t(r)] = R.p_off - R.caller_off;
+        nb += int64_t(nbuckets) * (int64_t(R.prm.ncells) * psub + 1);
+    }
+    if (nb >= INT32_MAX) return fail(ctx, PIC_E_ARG, "too many re-binning bins");
+    const int64_t nchunks = (nb + SCAN_CHUNK - 1) / SCAN_CHUNK;
+    // top of the score range (max over particles) fixes bucket 0
+    std::vector<float> hs(size_t(ctx->np));
+    HIP_TRY(ctx, hipMemcpyAsync(hs.data(), score, hs.size() * 4, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    float top = -1e30f;
+    for (float v : hs)
+        if (v == v) top = std::max(top, v);
+    int32_t *key = nullptr, *hist = nullptr, *sums = nullptr, *dest = nullptr, *nperm = nullptr;
+    int64_t *dbin = nullptr, *dshift = nullptr;
+    double *nsoa = nullptr;
+    int8_t *nk = nullptr;
+    uint8_t *nst = nullptr;
+    float *gcost = nullptr;
+    pic_status st = PIC_OK;
+    hipError_t e = hipSuccess;
+    std::vector<float> hg;
+    std::vector<int32_t> order;
+    std::vector<int8_t> prio;
+    if ((st = dev_alloc(ctx, &key, n)) || (st = dev_alloc(ctx, &hist, size_t(nb))) ||
+        (st = dev_alloc(ctx, &sums, size_t(nchunks))) || (st = dev_alloc(ctx, &dest, n)) ||
+        (st = dev_alloc(ctx, &nperm, n)) || (st = dev_alloc(ctx, &dbin, bin_off.size())) ||
+        (st = dev_alloc(ctx, &dshift, shift.size())) || (st = dev_alloc(ctx, &nsoa, 4 * n)) ||
+        (st = dev_alloc(ctx, &nk, n)) || (st = dev_alloc(ctx, &nst, n)) ||
+        (st = dev_alloc(ctx, &gcost, size_t(ctx->ngroups))))
+        goto out;
+    e = hipMemcpyAsync(dbin, bin_off.data(), bin_off.size() * 8, hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(dshift, shift.data(), shift.size() * 8, hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(hist, 0, size_t(nb) * 4, ctx->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(nperm, 0xFF, n * 4, ctx->stream);
+    // padding slots keep their contents: start the new arrays as copies
+    {
+        const double *soa[4] = {ctx->x, ctx->px, ctx->py, ctx->pz};
+        for (int a = 0; a < 4 && e == hipSuccess; ++a)
+            e = hipMemcpyAsync(nsoa + a * n, soa[a], n * 8, hipMemcpyDeviceToDevice, ctx->stream);
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(nk, ctx->kold, n, hipMemcpyDeviceToDevice, ctx->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(nst, ctx->status, n, hipMemcpyDeviceToDevice, ctx->stream);
+    if (e == hipSuccess) {
+        const int g = grid_for(slots, 256, 8192);
+        prebin_key_kernel<<<g, 256, 0, ctx->stream>>>(ctx->d_runs, ctx->group_run, ctx->x,
+                                                      ctx->perm, score, dbin, nbuckets, width, top,
+                                                      psub, slots, key, hist);
+        scan_sums_kernel<<<unsigned(nchunks), 256, 0, ctx->stream>>>(hist, nb, sums);
+        scan_top_kernel<<<1, 1024, 0, ctx->stream>>>(sums, int(nchunks));
+        scan_chunk_kernel<<<unsigned(nchunks), 256, 0, ctx->stream>>>(hist, nb, sums);
+        prebin_scatter_kernel<<<g, 256, 0, ctx->stream>>>(key, ctx->perm, ctx->group_run, dshift,
+                                                          slots, hist, dest);
+        permute_state_kernel<<<g, 256, 0, ctx->stream>>>(
+            dest, slots, ctx->x, ctx->px, ctx->py, ctx->pz, ctx->kold, ctx->status, ctx->perm,
+            nsoa, nsoa + n, nsoa + 2 * n, nsoa + 3 * n, nk, nst, nperm);
+        e = hipGetLastError();
+    }
+    {
+        double *soa[4] = {ctx->x, ctx->px, ctx->py, ctx->pz};
+        for (int a = 0; a < 4 && e == hipSuccess; ++a)
+            e = hipMemcpyAsync(soa[a], nsoa + a * n, n * 8, hipMemcpyDeviceToDevice, ctx->stream);
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(ctx->kold, nk, n, hipMemcpyDeviceToDevice, ctx->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(ctx->perm, nperm, n * 4, hipMemcpyDeviceToDevice, ctx->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(ctx->status, nst, n, hipMemcpyDeviceToDevice, ctx->stream);
+    // dispatch order: groups by predicted cost, heaviest first; raised
+    // priority for the prio_groups heaviest
+    if (e == hipSuccess) {
+        group_cost_kernel<<<(ctx->ngroups + 3) / 4, 256, 0, ctx->stream>>>(score, ctx->perm,
+                                                                           ctx->ngroups, gcost);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+        hg.resize(size_t(ctx->ngroups));
+        e = hipMemcpyAsync(hg.data(), gcost, hg.size() * 4, hipMemcpyDeviceToHost, ctx->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    }
+    if (e == hipSuccess) {
+        order.resize(hg.size());
+        std::iota(order.begin(), order.end(), 0);
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int32_t a, int32_t b) { return hg[size_t(a)] > hg[size_t(b)]; });
+        prio.assign(hg.size(), 0);
+        for (int32_t i = 0; i < std::min<int32_t>(prio_groups, ctx->ngroups); ++i)
+            if (hg[size_t(order[size_t(i)])] > -1e29f) prio[size_t(order[size_t(i)])] = 1;
+        e = hipMemcpyAsync(ctx->group_order, order.data(), order.size() * 4, hipMemcpyHostToDevice,
+                           ctx->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(ctx->group_prio, prio.data(), prio.size(), hipMemcpyHostToDevice,
+                               ctx->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    }
+    if (e != hipSuccess) st = fail(ctx, PIC_E_DEVICE, "prebin: %s", hipGetErrorString(e));
+out:
+    (void)hipStreamSynchronize(ctx->stream);
+    void *tmps[] = {key, hist, sums, dest, nperm, dbin, dshift, nsoa, nk, nst, gcost};
+    for (void *p : tmps)
+        if (p) (void)hipFree(p);
+    return st;
 }
 
 }  // extern "C"

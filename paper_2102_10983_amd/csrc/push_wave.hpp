@@ -38,6 +38,8 @@ __global__ void __launch_bounds__(64 * WPG) push_wave_kernel(PushArgs a)
     const int g = a.group_order[pos];
     const int run = a.group_run[g];
     const RunDesc &R = a.runs[run];
+    const int prio = a.group_prio[g];
+    if (prio) set_prio(prio);
     const int64_t n0 = a.n0 != NO_LEVEL ? a.n0 : R.n_cur;
     const int32_t slot0 = int32_t(mod_floor(n0 - P, R.D));
     const double ncm1 = double(R.ncells - 1);
@@ -158,7 +160,7 @@ __global__ void __launch_bounds__(64 * WPG) push_wave_kernel(PushArgs a)
             }
             done = true;
         } else {
-            __builtin_amdgcn_s_setprio(2);
+            set_prio(prio + 2);
             int32_t vo[P + 1];
 #pragma unroll
             for (int j = 0; j <= P; ++j) vo[j] = j * WWIN - lo;
@@ -205,7 +207,7 @@ __global__ void __launch_bounds__(64 * WPG) push_wave_kernel(PushArgs a)
                     x = x + dt_new * (px / g2);
                 }
             }
-            __builtin_amdgcn_s_setprio(0);
+            set_prio(prio);
             if (!done) status = PIC_PARTICLE_LOST;
         }
         }
@@ -261,6 +263,8 @@ __global__ void __launch_bounds__(64 * WPG) push_wave_fp32c_kernel(PushArgs a)
     const int g = a.group_order[pos];
     const int run = a.group_run[g];
     const RunDesc &R = a.runs[run];
+    const int prio = a.group_prio[g];
+    if (prio) set_prio(prio);
     const int64_t n0 = a.n0 != NO_LEVEL ? a.n0 : R.n_cur;
     const int32_t slot0 = int32_t(mod_floor(n0 - P, R.D));
     const int ncm2 = R.ncells - 2;
@@ -414,7 +418,7 @@ __global__ void __launch_bounds__(64 * WPG) push_wave_fp32c_kernel(PushArgs a)
             frc = e2 + e3;
             done = true;
         } else {
-            __builtin_amdgcn_s_setprio(2);
+            set_prio(prio + 2);
             double xi = double(cell) + (double(fr) + double(frc));
             double px = double(pxh) + double(pxl);
             double py = double(pyh) + double(pyl);
@@ -460,7 +464,7 @@ __global__ void __launch_bounds__(64 * WPG) push_wave_fp32c_kernel(PushArgs a)
                 const double g2 = sqrt(1.0 + ((px * px + py * py) + pz * pz));
                 xi = xi + rdx * (px / g2);
             }
-            __builtin_amdgcn_s_setprio(0);
+            set_prio(prio);
             if (!done) status = PIC_PARTICLE_LOST;
             const double fl = floor(xi);
             cell = (xi >= 0.0 && xi < double(R.ncells)) ? int(fl) : -1;

@@ -30,7 +30,13 @@ EXPORTS = ("pic_create", "pic_destroy", "pic_last_error", "pic_particles_set",
            "pic_fields_load_r", "pic_fields_load_lattice_r", "pic_source_set", "pic_advance",
            "pic_run_level", "pic_graph_capture", "pic_graph_launch", "pic_graph_release",
            "pic_run_counters", "pic_tune_set", "pic_tune_get", "pic_autotune",
-           "pic_group_count", "pic_order_set")
+           "pic_group_count", "pic_order_set", "pic_features", "pic_mlp_forward",
+           "pic_mlp_grad", "pic_mlp_adam", "pic_prebin")
+
+MLP_FEATURES = 8
+MLP_HIDDEN = 64
+MLP_NPARAM = 4801
+NO_LEVEL = -(1 << 63)
 
 
 class PicError(RuntimeError):
@@ -110,6 +116,12 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "pic_autotune": ([vp, i32, i32, C.POINTER(Tune), C.POINTER(dbl)], C.c_int),
         "pic_group_count": ([vp], i32),
         "pic_order_set": ([vp, vp, C.c_int], C.c_int),
+        "pic_features": ([vp, i64, vp, vp], C.c_int),
+        "pic_mlp_forward": ([vp, vp, vp, vp, i64, vp], C.c_int),
+        "pic_mlp_grad": ([vp, vp, vp, vp, i64, C.c_float, vp, vp, vp], C.c_int),
+        "pic_mlp_adam": ([vp, vp, vp, vp, i32, C.c_float, C.c_float, C.c_float, C.c_float, i32,
+                          vp], C.c_int),
+        "pic_prebin": ([vp, vp, i32, C.c_float, i32], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -331,6 +343,28 @@ class Pusher:
             raise ValueError("order must list every group once")
         self._check(self._lib.pic_order_set(self._ctx, o.ctypes.data, MEM_HOST))
 
+    def features(self, a0, n=None, out=None):
+        """Predictor features [num, 8] (FP32 device tensor) at level n (None:
+        each run's current level); a0 = one amplitude per run."""
+        torch = _torch()
+        a = np.ascontiguousarray(np.broadcast_to(np.asarray(a0, dtype=np.float32),
+                                                 (self.nruns,)))
+        if out is None:
+            out = torch.empty((self.num, MLP_FEATURES), dtype=torch.float32, device="cuda")
+        ptr = _dev_ptr(out, torch.float32, self.num * MLP_FEATURES) if self.num else None
+        lev = NO_LEVEL if n is None else int(n)
+        self._check(self._lib.pic_features(self._ctx, lev, a.ctypes.data, ptr))
+        return out
+
+    def prebin(self, score, nbuckets: int = 8, width: float = 1.0, prio_groups: int = 0):
+        """Re-bin every run's particles by predicted load (FP32 device
+        tensor, one score per caller index), heaviest groups first."""
+        torch = _torch()
+        ptr = _dev_ptr(score, torch.float32, self.num) if self.num else None
+        torch.cuda.current_stream().synchronize()
+        self._check(self._lib.pic_prebin(self._ctx, ptr, int(nbuckets), float(width),
+                                         int(prio_groups)))
+
     def ktrace_set(self, buf, n_first: int = 0, first: int = 0):
         """Record k for caller indices [first, first + buf.shape[1]) at steps
         n_first .. n_first + buf.shape[0] - 1 into the int8 device tensor buf."""
@@ -377,3 +411,59 @@ class Pusher:
             self._ctx, MEM_DEVICE, p("gamma", torch.float64), p("px", torch.float64),
             p("py", torch.float64), p("pz", torch.float64), p("x", torch.float64),
             p("k_last", torch.int8), p("status", torch.uint8), None))
+
+
+# -- load predictor network (module level: needs no context) ---------------
+def _stream_ptr():
+    torch = _torch()
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _mlp_status(st: int, what: str):
+    if st != 0:
+        raise PicError(st, what)
+
+
+def mlp_forward(w_bf16, norm, feat, out=None):
+    """out[i] = network(feat[i]) with BF16 weights (int16 tensor of the
+    bit patterns), on torch's current stream."""
+    torch = _torch()
+    L = load_library()
+    n = feat.shape[0]
+    if out is None:
+        out = torch.empty(n, dtype=torch.float32, device="cuda")
+    if n == 0:
+        return out
+    _mlp_status(L.pic_mlp_forward(_dev_ptr(w_bf16, torch.int16, MLP_NPARAM),
+                                  _dev_ptr(norm, torch.float32, 2 * MLP_FEATURES),
+                                  _dev_ptr(feat, torch.float32, n * MLP_FEATURES),
+                                  _dev_ptr(out, torch.float32, n), n, _stream_ptr()),
+                "mlp forward")
+    return out
+
+
+def mlp_grad(w, norm, feat, target, grad, loss, inv_total=None):
+    """Accumulate the MSE gradient (w.r.t. the FP32 master weights w, forward
+    in BF16) into grad and the loss into loss[0]."""
+    torch = _torch()
+    L = load_library()
+    n = feat.shape[0]
+    if n == 0:
+        return
+    inv = 1.0 / n if inv_total is None else float(inv_total)
+    _mlp_status(L.pic_mlp_grad(_dev_ptr(w, torch.float32, MLP_NPARAM),
+                               _dev_ptr(norm, torch.float32, 2 * MLP_FEATURES),
+                               _dev_ptr(feat, torch.float32, n * MLP_FEATURES),
+                               _dev_ptr(target, torch.float32, n), n, inv,
+                               _dev_ptr(grad, torch.float32, MLP_NPARAM),
+                               _dev_ptr(loss, torch.float32, 1), _stream_ptr()), "mlp grad")
+
+
+def mlp_adam(w, m, v, grad, t: int, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One bias-corrected Adam step (t >= 1) in place."""
+    torch = _torch()
+    L = load_library()
+    n = w.numel()
+    _mlp_status(L.pic_mlp_adam(_dev_ptr(w, torch.float32), _dev_ptr(m, torch.float32, n),
+                               _dev_ptr(v, torch.float32, n), _dev_ptr(grad, torch.float32, n),
+                               n, lr, beta1, beta2, eps, int(t), _stream_ptr()), "mlp adam")
