@@ -37,6 +37,7 @@
 #include "push_wave.hpp"
 #include "setup.hpp"
 #include "mlp.hpp"
+#include "push_fast.hpp"
 
 using namespace picsub;
 
@@ -276,7 +277,7 @@ void launch_wave(const PushArgs &a, int precision, hipStream_t s)
     if (precision == PIC_FP64)
         push_wave_kernel<P, WPG, Arith::IEEE64><<<grid, block, 0, s>>>(a);
     else if (precision == PIC_FP64_FAST)
-        push_wave_kernel<P, WPG, Arith::FAST64><<<grid, block, 0, s>>>(a);
+        push_fast_kernel<P, WPG><<<grid, block, 0, s>>>(a);
     else
         push_wave_fp32c_kernel<P, WPG><<<grid, block, 0, s>>>(a);
 }

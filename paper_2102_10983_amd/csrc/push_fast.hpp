@@ -1,0 +1,326 @@
+// push_fast.hpp -- FP64 push with refined hardware reciprocal and inverse
+// square root (pic_precision PIC_FP64_FAST) and a step-ahead field window.
+//
+// Same schedule as the IEEE wavefront kernel: one wavefront per 64-slot
+// group, all S steps of the launch, no waiting on other wavefronts.  What
+// differs is where the fields come from.  Lanes of a group are sorted by
+// position and a particle moves less than one cell per step (c dt < dx), so
+// while the group stays narrow, the nodes every lane can touch in step n+1
+// lie in a window of PF_NW nodes fixed by the cells of step n.  During step
+// n each lane loads its share of that window for the levels of step n+1
+// (2 (p + 1) rows of PF_NW nodes: two FP64 values per lane for p = 3) into
+// registers; at the end of step n they go to the wavefront's LDS.  The
+// decision, the k = 0 step and every sub-step then read LDS, and the global
+// load latency hides behind a whole step of arithmetic.  A group that has
+// spread wider falls back to direct gathers (k = 0) or a synchronously
+// staged window of up to WWIN nodes (sub-cycled steps).
+//
+// Arithmetic: the temporal combination (Eqs. (lagrange1-2), (lagrange1-3)),
+// the tent weights and the Boris update (Sec. III) with fused multiply-adds,
+// 1/gamma from v_rsq_f64 + two Newton steps and the Boris denominator from
+// v_rcp_f64 + two Newton steps; x is carried in node units.  p_z never
+// changes in this geometry (E along y, B along z), so 1 + p_z^2 is a
+// constant of each lane.
+#pragma once
+
+#include "common.hpp"
+
+namespace picsub {
+
+constexpr int PF_NW = 16;   // nodes per row of the step-ahead window (lane bits 0..3)
+
+// Field rings live in global memory; saying so lets the loads be global
+// (not generic) loads.
+typedef const __attribute__((address_space(1))) double *gdptr;
+
+template <int P, typename T, typename W>
+__device__ __forceinline__ double comb_fma(const T *__restrict__ f, const int32_t (&off)[P + 1],
+                                           int i, const W &L)
+{
+    double v = L[0] * f[off[0] + i];
+#pragma unroll
+    for (int j = 1; j <= P; ++j) v = fma(L[j], f[off[j] + i], v);
+    return v;
+}
+
+__device__ __forceinline__ double tent_fma(double w, double f0, double f1)
+{
+    return fma(w, f1 - f0, f0);
+}
+
+// Boris update with c = q dt_p / 2 (Sec. III): half kick, rotation by
+// t = c B / gamma, half kick.  p_z is untouched.
+__device__ __forceinline__ void boris_fma(double c, double E, double B, double onepz, double &px,
+                                          double &py)
+{
+    const double h = c * E;
+    const double mx = px, my = py + h;
+    const double ig = rsq_nr(fma(mx, mx, fma(my, my, onepz)));
+    const double t = (c * B) * ig;
+    const double sz = (2.0 * t) * rcp_nr(fma(t, t, 1.0));
+    const double ax = fma(my, t, mx);
+    const double ay = fma(-mx, t, my);
+    px = fma(ay, sz, mx);
+    py = fma(-ax, sz, my) + h;
+}
+
+// Sum_j L_j F_j at one node from the LDS window: p points at the node in
+// row 0, rows 2j (E) and 2j + 1 (B) are WWIN doubles apart.
+template <int P, typename W>
+__device__ __forceinline__ double comb_lds(const double *p, int field, const W &L)
+{
+    double v = L[0] * p[field * WWIN];
+#pragma unroll
+    for (int j = 1; j <= P; ++j) v = fma(L[j], p[(2 * j + field) * WWIN], v);
+    return v;
+}
+
+template <int P, int WPG>
+__global__ void __launch_bounds__(64 * WPG) push_fast_kernel(PushArgs a)
+{
+    constexpr int ROWS = 2 * (P + 1);                 // row 2j: E of level j, 2j+1: B
+    constexpr int NPF = (ROWS * PF_NW + 63) / 64;     // window values per lane
+    constexpr int STRIDE = 2 * (P + 1);               // weight-table entry
+    static_assert(PF_NW == 16, "the step-ahead load maps lane bits 4, 5 to field, level");
+    __shared__ double sw_all[WPG][ROWS * WWIN];
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int pos = blockIdx.x * WPG + wv;
+    if (pos >= a.ngroups) return;                      // whole wavefront: no barrier below
+    double *sw = sw_all[wv];
+    const int g = __builtin_amdgcn_readfirstlane(a.group_order[pos]);
+    const int run = __builtin_amdgcn_readfirstlane(a.group_run[g]);
+    const int prio = __builtin_amdgcn_readfirstlane(a.group_prio[g]);
+    if (prio) set_prio(prio);
+    // the run's constants, once, in scalar registers
+    const RunDesc &RD = a.runs[run];
+    const gdptr ringE = (gdptr)RD.ringE;
+    const gdptr ringB = (gdptr)RD.ringB;
+    const double x_origin = RD.x_origin, dx = RD.dx, dt = RD.dt, qm = RD.qm;
+    const double psi_max = RD.psi_max, dtdx = RD.dtdx;
+    const int32_t D = RD.D, ncells = RD.ncells, kmax = RD.kmax, margin = RD.margin;
+    const int64_t n0 = a.n0 != NO_LEVEL ? a.n0 : RD.n_cur;
+    const int S_run = run_steps(a, RD, n0);
+    const int64_t p_off = RD.p_off, np = RD.np;
+    const int32_t slot0 = int32_t(mod_floor(n0 - P, D));
+    const double ncm1 = double(ncells - 1);
+    const double c0 = 0.5 * qm * dt;
+    const double *LB1 = a.wtab + (P + 1);              // B weights of (k = 0, j = 1): s = 1/2
+    const int rad = (PF_NW - 2 * margin - 4) / 2;      // cell spread the window allows
+    WaveCounts cnt;
+    cnt.zero();
+
+    const int64_t s = int64_t(g) * 64 + lane;
+    const bool mine = s - p_off < np;
+    double x = 0, px = 0, py = 0, pz = 0, onepz = 1, ig = 1;   // x in node units
+    int kold = 0;
+    uint8_t status = PIC_PARTICLE_LOST;
+    int64_t kt_u = -1;
+    if (mine) {
+        x = (a.x[s] - x_origin) / dx;
+        px = a.px[s];
+        py = a.py[s];
+        pz = a.pz[s];
+        onepz = fma(pz, pz, 1.0);
+        ig = rsq_nr(fma(px, px, fma(py, py, onepz)));
+        kold = a.kold[s];
+        status = a.status[s];
+        if (a.ktrace) {
+            const int64_t u = a.perm[s] - a.kt_first;
+            if (u >= 0 && u < a.kt_count) kt_u = u;
+        }
+    }
+    bool moved = false;
+    bool win = false;        // LDS holds this step's levels on nodes [wlo, wlo + PF_NW)
+    int wlo = 0;
+    double pf[NPF];
+
+    for (int st = 0; st < S_run; ++st) {
+        const int64_t n = n0 + st;
+        Levels<P> lv;
+        lv.at(slot0, st, D, ncells);
+        const bool live = status == PIC_PARTICLE_LIVE && x >= 0.5 && x < ncm1;
+        const bool left = status == PIC_PARTICLE_LIVE && !live;
+        cnt.lost += __popcll(__ballot(left));
+        if (left) status = PIC_PARTICLE_LOST;
+        if (!live) ktrace_put(a, kt_u, n, -1);
+        const uint64_t lmask = __ballot(live);
+        if (!lmask) {
+            for (int s2 = st + 1; s2 < S_run; ++s2) ktrace_put(a, kt_u, n0 + s2, -1);
+            break;
+        }
+        const double fl = floor(x);
+        const int cell = int(fl);
+        // reference cell: the first live lane's
+        const int cref = __builtin_amdgcn_readlane(cell, __ffsll((unsigned long long)lmask) - 1);
+
+        // Step-ahead loads: the levels of step n+1 on the nodes any lane can
+        // reach from this step's cells (all within rad of cref).
+        const bool pf_next = st + 1 < S_run && rad >= 0 &&
+                             __all(!live || (cell >= cref - rad && cell <= cref + rad));
+        const int nlo = cref - rad - margin - 1;
+        if (pf_next) {
+            Levels<P> ln;
+            ln.at(slot0, st + 1, D, ncells);
+#pragma unroll
+            for (int h = 0; h < NPF; ++h) {
+                // value e = lane + 64 h: row e / 16 (level e / 32, field
+                // (e / 16) & 1), node nlo + e % 16
+                if (lane + 64 * h < ROWS * PF_NW) {
+                    const int node = min(max(nlo + (lane & (PF_NW - 1)), 0), ncells - 1);
+                    const int32_t off = (lane & 32) ? ln.off[2 * h + 1] : ln.off[2 * h];
+                    const gdptr src = (lane & 16) ? ringB : ringE;
+                    pf[h] = src[off + node];
+                }
+            }
+        }
+
+        // Does the window loaded during the previous step cover every lane?
+        const bool use_win =
+            win && __all(!live || (cell - margin >= wlo && cell + margin + 1 < wlo + PF_NW));
+
+        // decision: B at (x_n, s = 1/2), 1/gamma of the stored momentum
+        int k = 0;
+        double Bd = 0.0;
+        bool clamped = false;
+        if (live) {
+            double b0, b1;
+            if (use_win) {
+                const double *p = sw + (cell - wlo);
+                b0 = comb_lds<P>(p, 1, LB1);
+                b1 = comb_lds<P>(p + 1, 1, LB1);
+            } else {
+                b0 = comb_fma<P>(ringB, lv.off, cell, LB1);
+                b1 = comb_fma<P>(ringB, lv.off, cell + 1, LB1);
+            }
+            Bd = tent_fma(x - fl, b0, b1);
+            const double psi0 = fabs(c0 * Bd) * ig;
+            double lim = psi_max;
+            while (psi0 > lim && k < kmax) {
+                ++k;
+                lim = lim * 4.0;
+            }
+            clamped = psi0 > lim;
+            ktrace_put(a, kt_u, n, int8_t(k));
+        }
+        cnt.clamps += __popcll(__ballot(clamped));
+        const bool heavy = live && k > 0;
+
+        // A sub-cycled step outside the step-ahead window stages its own.
+        bool lds = use_win;
+        int base = wlo;
+        if (!use_win && __any(heavy)) {
+            const int lo = max(__builtin_amdgcn_readfirstlane(
+                                   wave_min(heavy ? cell - margin : INT_MAX)), 0);
+            const int hi = min(__builtin_amdgcn_readfirstlane(
+                                   wave_max(heavy ? cell + margin : INT_MIN)), ncells - 1);
+            if (hi - lo + 1 <= WWIN) {
+                wave_lds_sync();
+                for (int q = lane; q <= hi - lo; q += 64) {
+#pragma unroll
+                    for (int j = 0; j <= P; ++j) {
+                        sw[(2 * j) * WWIN + q] = ringE[lv.off[j] + lo + q];
+                        sw[(2 * j + 1) * WWIN + q] = ringB[lv.off[j] + lo + q];
+                    }
+                }
+                wave_lds_sync();
+                base = lo;
+                lds = true;
+            }
+        }
+
+        bool done = false;
+        if (live) {
+            moved = true;
+            const int ko = kold < 0 ? k : kold;
+            kold = k;
+            const double dt_new = ldexp(dt, -2 * k);
+            const double dt_old = ldexp(dt, -2 * ko);
+            const double rdx = ldexp(dtdx, -2 * k);
+            const double c1 = 0.25 * qm * (dt_old + dt_new);   // c of the transition push
+            if (k == 0) {
+                // s = 1/2 is the time of level n: E's weights are (0, .., 0, 1)
+                const double uE = x - 0.5;
+                const double flE = floor(uE);
+                const int iE = int(flE);
+                double e0, e1;
+                if (use_win) {
+                    const double *p = sw + (2 * P) * WWIN + (iE - wlo);
+                    e0 = p[0];
+                    e1 = p[1];
+                } else {
+                    e0 = ringE[lv.off[P] + iE];
+                    e1 = ringE[lv.off[P] + iE + 1];
+                }
+                boris_fma(c1, tent_fma(uE - flE, e0, e1), Bd, onepz, px, py);
+                ig = rsq_nr(fma(px, px, fma(py, py, onepz)));
+                x = fma(rdx, px * ig, x);
+                done = true;
+            } else {
+                set_prio(prio + 2);
+                const int nsub = 1 << (2 * k);
+                const double cn = 0.5 * qm * dt_new;
+                const double *Wk = a.wtab + wtab_offset(k) * STRIDE;
+                done = true;
+                for (int j = 1; j <= nsub; ++j, Wk += STRIDE) {
+                    if (j > 1 && !(x >= 0.5 && x < ncm1)) {
+                        done = false;
+                        break;
+                    }
+                    const double fb = floor(x);
+                    const int ib = int(fb);
+                    const double uE = x - 0.5;
+                    const double fe = floor(uE);
+                    const int ie = int(fe);
+                    double bb0, bb1, e0, e1;
+                    if (lds) {
+                        const double *pb = sw + (ib - base);
+                        const double *pe = sw + (ie - base);
+                        bb0 = comb_lds<P>(pb, 1, Wk + P + 1);
+                        bb1 = comb_lds<P>(pb + 1, 1, Wk + P + 1);
+                        e0 = comb_lds<P>(pe, 0, Wk);
+                        e1 = comb_lds<P>(pe + 1, 0, Wk);
+                    } else {
+                        bb0 = comb_fma<P>(ringB, lv.off, ib, Wk + P + 1);
+                        bb1 = comb_fma<P>(ringB, lv.off, ib + 1, Wk + P + 1);
+                        e0 = comb_fma<P>(ringE, lv.off, ie, Wk);
+                        e1 = comb_fma<P>(ringE, lv.off, ie + 1, Wk);
+                    }
+                    boris_fma(j == 1 ? c1 : cn, tent_fma(uE - fe, e0, e1),
+                              tent_fma(x - fb, bb0, bb1), onepz, px, py);
+                    ig = rsq_nr(fma(px, px, fma(py, py, onepz)));
+                    x = fma(rdx, px * ig, x);
+                }
+                set_prio(prio);
+                if (!done) status = PIC_PARTICLE_LOST;
+            }
+        }
+        cnt.steps_done(done, k);
+        cnt.lost += __popcll(__ballot(live && !done));
+
+        // hand the step-ahead window to LDS for the next step
+        if (pf_next) {
+            wave_lds_sync();
+#pragma unroll
+            for (int h = 0; h < NPF; ++h) {
+                const int e = lane + 64 * h;
+                if (e < ROWS * PF_NW) sw[(e / PF_NW) * WWIN + e % PF_NW] = pf[h];
+            }
+            wave_lds_sync();
+            wlo = nlo;
+        }
+        win = pf_next;
+    }
+    if (mine) {
+        if (moved) {
+            a.x[s] = x_origin + x * dx;
+            a.px[s] = px;
+            a.py[s] = py;
+        }
+        a.kold[s] = int8_t(kold);
+        a.status[s] = status;
+    }
+    cnt.flush(a.cnt + (int64_t(run) * NSLOT + pos % NSLOT) * NCNT, lane);
+}
+
+}  // namespace picsub

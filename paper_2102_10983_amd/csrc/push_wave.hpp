@@ -30,15 +30,15 @@ __global__ void __launch_bounds__(64 * WPG) push_wave_kernel(PushArgs a)
     __shared__ double sE_all[WPG][(P + 1) * WWIN];
     __shared__ double sB_all[WPG][(P + 1) * WWIN];
     const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int pos = blockIdx.x * WPG + wv;
     if (pos >= a.ngroups) return;              // whole wavefront: no barrier below
     double *sE = sE_all[wv];
     double *sB = sB_all[wv];
-    const int g = a.group_order[pos];
-    const int run = a.group_run[g];
-    const RunDesc &R = a.runs[run];
-    const int prio = a.group_prio[g];
+    const int g = __builtin_amdgcn_readfirstlane(a.group_order[pos]);
+    const int run = __builtin_amdgcn_readfirstlane(a.group_run[g]);
+    const RunDesc R = a.runs[run];                 // wave-uniform: scalar registers
+    const int prio = __builtin_amdgcn_readfirstlane(a.group_prio[g]);
     if (prio) set_prio(prio);
     const int64_t n0 = a.n0 != NO_LEVEL ? a.n0 : R.n_cur;
     const int32_t slot0 = int32_t(mod_floor(n0 - P, R.D));
@@ -253,17 +253,17 @@ __global__ void __launch_bounds__(64 * WPG) push_wave_fp32c_kernel(PushArgs a)
     __shared__ float sBh_all[WPG][WWIN];
     __shared__ float sEn_all[WPG][WWIN];
     const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int pos = blockIdx.x * WPG + wv;
     if (pos >= a.ngroups) return;
     double *sE = sE_all[wv];
     double *sB = sB_all[wv];
     float *sBh = sBh_all[wv];
     float *sEn = sEn_all[wv];
-    const int g = a.group_order[pos];
-    const int run = a.group_run[g];
-    const RunDesc &R = a.runs[run];
-    const int prio = a.group_prio[g];
+    const int g = __builtin_amdgcn_readfirstlane(a.group_order[pos]);
+    const int run = __builtin_amdgcn_readfirstlane(a.group_run[g]);
+    const RunDesc R = a.runs[run];                 // wave-uniform: scalar registers
+    const int prio = __builtin_amdgcn_readfirstlane(a.group_prio[g]);
     if (prio) set_prio(prio);
     const int64_t n0 = a.n0 != NO_LEVEL ? a.n0 : R.n_cur;
     const int32_t slot0 = int32_t(mod_floor(n0 - P, R.D));
