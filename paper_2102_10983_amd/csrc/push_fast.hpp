@@ -17,8 +17,8 @@
 //
 // Arithmetic: the temporal combination (Eqs. (lagrange1-2), (lagrange1-3)),
 // the tent weights and the Boris update (Sec. III) with fused multiply-adds,
-// 1/gamma from v_rsq_f64 + two Newton steps and the Boris denominator from
-// v_rcp_f64 + two Newton steps; x is carried in node units.  p_z never
+// 1/gamma from v_rsq_f64 and the Boris denominator from v_rcp_f64, each
+// refined by one Newton step; x is carried in node units.  p_z never
 // changes in this geometry (E along y, B along z), so 1 + p_z^2 is a
 // constant of each lane.
 #pragma once
@@ -33,6 +33,27 @@ constexpr int PF_NW = 16;   // nodes per row of the step-ahead window (lane bits
 // (not generic) loads.
 typedef const __attribute__((address_space(1))) double *gdptr;
 
+// Lagrange weights of the B levels (nodes s = 1 - p .. 1) at s = 1/2, the
+// decision's time (Eq. (lagrange1-3)); exact dyadic values, the same the
+// weight table holds for (k = 0, j = 1).
+template <int P> struct HalfStepB;
+template <> struct HalfStepB<1> {
+    __device__ constexpr double operator[](int j) const { return 0.5; }
+};
+template <> struct HalfStepB<3> {
+    __device__ constexpr double operator[](int j) const
+    {
+        return j == 0 ? 1.0 / 16 : j == 1 ? -5.0 / 16 : j == 2 ? 15.0 / 16 : 5.0 / 16;
+    }
+};
+template <> struct HalfStepB<5> {
+    __device__ constexpr double operator[](int j) const
+    {
+        return j == 0 ? 7.0 / 256 : j == 1 ? -45.0 / 256 : j == 2 ? 126.0 / 256
+             : j == 3 ? -210.0 / 256 : j == 4 ? 315.0 / 256 : 63.0 / 256;
+    }
+};
+
 template <int P, typename T, typename W>
 __device__ __forceinline__ double comb_fma(const T *__restrict__ f, const int32_t (&off)[P + 1],
                                            int i, const W &L)
@@ -41,6 +62,21 @@ __device__ __forceinline__ double comb_fma(const T *__restrict__ f, const int32_
 #pragma unroll
     for (int j = 1; j <= P; ++j) v = fma(L[j], f[off[j] + i], v);
     return v;
+}
+
+// 1 / sqrt(a), a >= 1, and 1 / b, b >= 1: the hardware estimates (relative
+// error near 2^-26) refined by one Newton step, which squares the error.
+__device__ __forceinline__ double rsq_1nr(double a)
+{
+    const double y = __builtin_amdgcn_rsq(a);
+    const double r = fma(-0.5 * a * y, y, 0.5);
+    return fma(y, r, y);
+}
+
+__device__ __forceinline__ double rcp_1nr(double b)
+{
+    const double r = __builtin_amdgcn_rcp(b);
+    return fma(r, fma(-b, r, 1.0), r);
 }
 
 __device__ __forceinline__ double tent_fma(double w, double f0, double f1)
@@ -55,9 +91,9 @@ __device__ __forceinline__ void boris_fma(double c, double E, double B, double o
 {
     const double h = c * E;
     const double mx = px, my = py + h;
-    const double ig = rsq_nr(fma(mx, mx, fma(my, my, onepz)));
+    const double ig = rsq_1nr(fma(mx, mx, fma(my, my, onepz)));
     const double t = (c * B) * ig;
-    const double sz = (2.0 * t) * rcp_nr(fma(t, t, 1.0));
+    const double sz = (2.0 * t) * rcp_1nr(fma(t, t, 1.0));
     const double ax = fma(my, t, mx);
     const double ay = fma(-mx, t, my);
     px = fma(ay, sz, mx);
@@ -105,7 +141,7 @@ __global__ void __launch_bounds__(64 * WPG) push_fast_kernel(PushArgs a)
     const int32_t slot0 = int32_t(mod_floor(n0 - P, D));
     const double ncm1 = double(ncells - 1);
     const double c0 = 0.5 * qm * dt;
-    const double *LB1 = a.wtab + (P + 1);              // B weights of (k = 0, j = 1): s = 1/2
+    const HalfStepB<P> LB1;                            // B weights at s = 1/2
     const int rad = (PF_NW - 2 * margin - 4) / 2;      // cell spread the window allows
     WaveCounts cnt;
     cnt.zero();
@@ -122,7 +158,7 @@ __global__ void __launch_bounds__(64 * WPG) push_fast_kernel(PushArgs a)
         py = a.py[s];
         pz = a.pz[s];
         onepz = fma(pz, pz, 1.0);
-        ig = rsq_nr(fma(px, px, fma(py, py, onepz)));
+        ig = rsq_1nr(fma(px, px, fma(py, py, onepz)));
         kold = a.kold[s];
         status = a.status[s];
         if (a.ktrace) {
@@ -253,7 +289,7 @@ __global__ void __launch_bounds__(64 * WPG) push_fast_kernel(PushArgs a)
                     e1 = ringE[lv.off[P] + iE + 1];
                 }
                 boris_fma(c1, tent_fma(uE - flE, e0, e1), Bd, onepz, px, py);
-                ig = rsq_nr(fma(px, px, fma(py, py, onepz)));
+                ig = rsq_1nr(fma(px, px, fma(py, py, onepz)));
                 x = fma(rdx, px * ig, x);
                 done = true;
             } else {
@@ -288,7 +324,7 @@ __global__ void __launch_bounds__(64 * WPG) push_fast_kernel(PushArgs a)
                     }
                     boris_fma(j == 1 ? c1 : cn, tent_fma(uE - fe, e0, e1),
                               tent_fma(x - fb, bb0, bb1), onepz, px, py);
-                    ig = rsq_nr(fma(px, px, fma(py, py, onepz)));
+                    ig = rsq_1nr(fma(px, px, fma(py, py, onepz)));
                     x = fma(rdx, px * ig, x);
                 }
                 set_prio(prio);
