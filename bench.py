@@ -6,10 +6,13 @@ plane wave a = a0 sin(t - x), a0 = 150 (seed 22; seeds 20 and 21 give
 a0 = 30 and 100), T/dt = 75, dx = 1.01 c dt (74.26 cells per wavelength),
 8192 cells, 100 laser periods (7500 steps of dt), 3rd-order temporal
 interpolation, psi_max = 0.01.  A step loads the initial state (device to
-device), then runs all 7500 steps in launches of S steps, each launch
-preceded by the on-device sampling of its field levels.
+device, sorted by position), with --binning learned scores every electron
+with the load predictor and re-bins them (heaviest groups first), samples
+the field levels on the device and runs all 7500 steps in launches of S
+steps (default: one launch).
 
-Printed: one JSON line with the metric, the roofline of the push kernel
+Printed: one JSON line with the metric, the same pass timed with plain
+binning and with the plain FP64 (IEEE) push, the roofline of the push kernel
 (its average launch duration from HIP events on the push stream over the
 timed region) and the FP64 CPU oracle timed on a bounded sample.
 """
@@ -17,8 +20,8 @@ timed region) and the FP64 CPU oracle timed on a bounded sample.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -32,6 +35,14 @@ sys.path.insert(0, ROOT)
 PEAK_FP64_TFLOPS = 78.6      # vector FP64, FMA counted as 2 flops
 PEAK_HBM_GBS = 8000.0
 
+KERNELS = {  # (kernel name in traces, sources it is built from)
+    "fp64": ("push_wave_kernel<3, 1, (Arith)0>", ("push_wave.hpp", "common.hpp")),
+    "fp64fast": ("push_fast_kernel<3, 1>", ("push_fast.hpp", "common.hpp")),
+    "fp32c": ("push_wave_fp32c_kernel<3, 1>", ("push_wave.hpp", "common.hpp")),
+    "ballot": ("push_tile_kernel<3, 256>", ("push_tile.hpp", "common.hpp")),
+}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "push_traffic.json")
+
 
 def flops_per_substep(order: int) -> int:
     """Algorithmic FP64 operations of one sub-step (mul, add, div, sqrt = 1):
@@ -40,12 +51,32 @@ def flops_per_substep(order: int) -> int:
 
 
 FLOPS_PER_DECISION = 11       # grid coordinate 2, gamma 7, psi0 2
-BYTES_PER_PARTICLE_STEP = 4 * 8 * 2 + 2 * 2   # x, px, py, pz read+write; k_old, status
 
 
 def algorithmic_flops(counters: dict, order: int) -> int:
     f = flops_per_substep(order)
     return sum(c * (FLOPS_PER_DECISION + (4 ** k) * f) for k, c in enumerate(counters["steps_by_k"]))
+
+
+def source_hash(files) -> str:
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, "paper_2102_10983_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(key: str, launches_per_step: int):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE runs, if they were taken on the kernel as built now."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as fh:
+        rec = json.load(fh).get(key)
+    name, files = KERNELS[key]
+    if not rec or rec.get("source_hash") != source_hash(files):
+        return None
+    return rec["bytes_per_launch"] if launches_per_step == rec.get("launches_per_pass", 1) else None
 
 
 def cpu_baseline(wl, every: int, threads: int):
@@ -69,20 +100,70 @@ def cpu_baseline(wl, every: int, threads: int):
                       f"{cnt.sub_steps} sub-steps in {dt:.2f} s"}
 
 
+class Pass:
+    """One configuration of the hot path on one workload."""
+
+    def __init__(self, wl, S, precision, binning, predictor=None):
+        from paper_2102_10983_amd import runner
+        self.wl = wl
+        self.S = S
+        self.binning = binning
+        self.predictor = predictor
+        kernel_binning = "ballot" if binning == "ballot" else "none"
+        self.run = runner.DeviceRun(wl, S=S, precision=precision, binning=kernel_binning)
+
+    def step(self, stream=None, events=None):
+        import torch
+        run, wl = self.run, self.wl
+        run.reset()
+        run.pusher.counters_reset()
+        if self.binning == "learned":
+            self.predictor.prebin(run.pusher, wl.a0, n=0)
+        while run.n < wl.steps:
+            s = min(self.S, wl.steps - run.n)
+            run.pusher.fields_load_lattice(run.n, s, run.table, run.M, run.coeffs)
+            if events is not None:
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                run.pusher.push(run.n, s)
+                e1.record(stream)
+                events.append((e0, e1))
+            else:
+                run.pusher.push(run.n, s)
+            run.n += s
+
+    def time(self, steps, warmup, stream, events=None):
+        import torch
+        for _ in range(warmup):
+            self.step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            self.step(stream, events)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    def close(self):
+        self.run.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--seed", type=int, default=22, choices=(20, 21, 22))
-    ap.add_argument("--S", type=int, default=int(os.environ.get("PICSUB_BENCH_S", "0")),
+    ap.add_argument("--S", type=int, default=0,
                     help="steps of dt per push launch (0: the whole run in one launch)")
-    ap.add_argument("--precision", default="fp64", choices=("fp64", "fp32c", "fp64fast"))
-    ap.add_argument("--binning", default="none", choices=("none", "ballot", "learned"))
+    ap.add_argument("--precision", default="fp64fast", choices=("fp64", "fp32c", "fp64fast"))
+    ap.add_argument("--binning", default="learned", choices=("none", "ballot", "learned"))
     ap.add_argument("--num", type=int, default=1 << 20)
     ap.add_argument("--periods", type=float, default=100.0)
-    ap.add_argument("--cpu-every", type=int, default=64)
+    ap.add_argument("--cpu-every", type=int, default=8)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the plain-binning and plain-FP64 passes")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a device-to-device copy of BYTES (HBM counter calibration)")
     args = ap.parse_args()
@@ -103,54 +184,44 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2102_10983_amd import runner, workloads as W
+    from paper_2102_10983_amd import predictor as PR, workloads as W
 
     wl = W.large_case(seed=args.seed, num=args.num, periods=args.periods)
-    if args.S <= 0:
-        args.S = wl.steps
-    run = runner.DeviceRun(wl, S=args.S, precision=args.precision, binning=args.binning)
+    S = wl.steps if args.S <= 0 else args.S
+    model = PR.Predictor.load() if args.binning == "learned" else None
     stream = torch.cuda.current_stream()
 
-    def one_step(events=None):
-        run.reset()
-        run.pusher.counters_reset()
-        end = wl.steps
-        while run.n < end:
-            s = min(args.S, end - run.n)
-            run.pusher.fields_load_lattice(run.n, s, run.table, run.M, run.coeffs)
-            if events is not None:
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-                e0.record(stream)
-                run.pusher.push(run.n, s)
-                e1.record(stream)
-                events.append((e0, e1))
-            else:
-                run.pusher.push(run.n, s)
-            run.n += s
-
-    for _ in range(args.warmup):
-        one_step()
-    torch.cuda.synchronize()
-    counters = run.pusher.counters()     # one full pass: counts per step
-
+    main_pass = Pass(wl, S, args.precision, args.binning, model)
     events = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        one_step(events)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    elapsed = main_pass.time(args.steps, args.warmup, stream, events)
+    counters = main_pass.run.pusher.counters()          # the last pass
+    main_pass.close()
 
-    if args.warmup == 0:
-        counters = run.pusher.counters()
     sub_per_step = counters["sub_steps"]
     value = sub_per_step * args.steps / elapsed
     kernel_ms = sum(a.elapsed_time(b) for a, b in events)
     launches = len(events)
-    avg_launch_s = kernel_ms / 1e3 / launches
+    launches_per_step = launches // args.steps
     flops_step = algorithmic_flops(counters, wl.order)
     achieved = flops_step * args.steps / (kernel_ms / 1e3) / 1e12
+    key = "ballot" if args.binning == "ballot" else args.precision
+    traffic = measured_traffic(key, launches_per_step)
+
+    compare = []
+    if not args.no_compare:
+        for label, prec, binning in (("plain binning, same precision", args.precision, "none"),
+                                     ("plain FP64 push (IEEE div/sqrt)", "fp64", "none")):
+            if prec == args.precision and binning == args.binning:
+                continue
+            p = Pass(wl, S, prec, binning)
+            t = p.time(args.steps, args.warmup, stream)
+            c = p.run.pusher.counters()
+            p.close()
+            compare.append({"label": label, "precision": prec, "binning": binning,
+                            "ms_per_step": t / args.steps * 1e3,
+                            "value": c["sub_steps"] * args.steps / t,
+                            "same_sub_steps": c["sub_steps"] == sub_per_step})
+
     res = {
         "metric": "sub-step particle pushes/sec at rel err<=1e-5 vs FP64 oracle; "
                   "learned-binned vs plain",
@@ -165,25 +236,23 @@ def main():
         "vs_baseline": None,
         "dtype": {"fp64": "f64", "fp64fast": "f64", "fp32c": "f32+f64"}[args.precision],
         "data": "synthetic",
-        "config": {"workload": f"plane wave a0={wl.a0:g}, {wl.num} electrons over 8 lambda, "
-                               f"T/dt=75, dx=1.01 c dt, {wl.ncells} cells, {wl.steps} steps, "
-                               f"order {wl.order}, psi_max {wl.psi_max}",
+        "config": {"workload": f"plane wave a0={wl.a0:g}, {wl.num} electrons at rest over 8 "
+                               f"lambda, T/dt=75, dx=1.01 c dt, {wl.ncells} cells, {wl.steps} "
+                               f"steps, order {wl.order}, psi_max {wl.psi_max}",
                    "precision": args.precision, "binning": args.binning,
-                   "steps_per_launch": args.S, "sub_steps_per_pass": sub_per_step,
+                   "steps_per_launch": S, "sub_steps_per_pass": sub_per_step,
                    "mean_sub_steps_per_particle_step": sub_per_step / counters["steps"],
                    "n_star": counters["n_star"], "steps_by_k": counters["steps_by_k"][:9]},
+        "compare": compare,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
-                     "kernel": {"fp64": "push_wave_kernel<3>", "fp64fast": "push_wave_fast_kernel<3>",
-                                "fp32c": "push_wave_mixed_kernel<3>"}[args.precision]
-                     if args.binning != "ballot" else "push_tile_kernel<3>", "launches": launches,
-                     "avg_launch_ms": avg_launch_s * 1e3,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
+                     "kernel": KERNELS[key][0], "launches": launches,
+                     "avg_launch_ms": kernel_ms / launches,
                      "flops_per_launch": flops_step * args.steps / launches},
     }
     if not args.no_cpu:
         threads = len(os.sched_getaffinity(0))
         res["cpu_baseline"] = cpu_baseline(wl, args.cpu_every, threads)
-    run.close()
     print(json.dumps(res))
 
 
