@@ -71,17 +71,20 @@ typedef enum {
                            steps.  Not within 1e-5 of FP64 for ultra-
                            relativistic electrons (gamma amplifies FP32
                            rounding of the transverse force) */
-    PIC_FP64_FAST = 2   /* FP64 with hardware reciprocal / rsqrt estimates
-                           refined by Newton steps (faithful rounding),
-                           positions in node units, 1/gamma reused by the
-                           next decision */
+    PIC_FP64_FAST = 2   /* FP64 with fused multiply-adds, the hardware
+                           reciprocal / rsqrt estimates refined by one Newton
+                           step, positions in node units, 1/gamma reused by
+                           the next decision, and the next step's field
+                           window loaded into LDS one step ahead; within
+                           1e-9 of PIC_FP64 in practice (not bit-identical) */
 } pic_precision;
 
 /* how particles are grouped onto wavefronts for the sub-step loop */
 typedef enum {
     PIC_BIN_NONE = 0,    /* one particle per lane, no regrouping */
     PIC_BIN_BALLOT = 1,  /* per-step compaction by k inside a workgroup */
-    PIC_BIN_LEARNED = 2  /* BALLOT plus an MLP pre-partition by predicted k */
+    PIC_BIN_LEARNED = 2  /* the wavefront kernels of NONE; the caller re-bins
+                            by predicted load with pic_prebin (below) */
 } pic_binning;
 
 #define PIC_PARTICLE_LIVE 0u
