@@ -167,19 +167,28 @@ __global__ void __launch_bounds__(64 * WPG) push_fast_kernel(PushArgs a)
         }
     }
     bool moved = false;
+    const bool tracing = a.ktrace != nullptr;
     bool win = false;        // LDS holds this step's levels on nodes [wlo, wlo + PF_NW)
     int wlo = 0;
     double pf[NPF];
 
+    // ring offsets of levels n - P .. n + 1 (scalar registers), moved on by
+    // one slot per step
+    int32_t lvo[P + 2];
+#pragma unroll
+    for (int j = 0; j <= P + 1; ++j) lvo[j] = int32_t(mod_floor(slot0 + j, D)) * ncells;
+    const int32_t ring_end = D * ncells;
+
     for (int st = 0; st < S_run; ++st) {
         const int64_t n = n0 + st;
         Levels<P> lv;
-        lv.at(slot0, st, D, ncells);
+#pragma unroll
+        for (int j = 0; j <= P; ++j) lv.off[j] = lvo[j];
         const bool live = status == PIC_PARTICLE_LIVE && x >= 0.5 && x < ncm1;
         const bool left = status == PIC_PARTICLE_LIVE && !live;
         cnt.lost += __popcll(__ballot(left));
         if (left) status = PIC_PARTICLE_LOST;
-        if (!live) ktrace_put(a, kt_u, n, -1);
+        if (tracing && !live) ktrace_put(a, kt_u, n, -1);
         const uint64_t lmask = __ballot(live);
         if (!lmask) {
             for (int s2 = st + 1; s2 < S_run; ++s2) ktrace_put(a, kt_u, n0 + s2, -1);
@@ -197,7 +206,8 @@ __global__ void __launch_bounds__(64 * WPG) push_fast_kernel(PushArgs a)
         const int nlo = cref - rad - margin - 1;
         if (pf_next) {
             Levels<P> ln;
-            ln.at(slot0, st + 1, D, ncells);
+#pragma unroll
+            for (int j = 0; j <= P; ++j) ln.off[j] = lvo[j + 1];
 #pragma unroll
             for (int h = 0; h < NPF; ++h) {
                 // value e = lane + 64 h: row e / 16 (level e / 32, field
@@ -217,7 +227,7 @@ __global__ void __launch_bounds__(64 * WPG) push_fast_kernel(PushArgs a)
 
         // decision: B at (x_n, s = 1/2), 1/gamma of the stored momentum
         int k = 0;
-        double Bd = 0.0;
+        double Bd = 0.0, psi0 = 0.0;
         bool clamped = false;
         if (live) {
             double b0, b1;
@@ -230,16 +240,20 @@ __global__ void __launch_bounds__(64 * WPG) push_fast_kernel(PushArgs a)
                 b1 = comb_fma<P>(ringB, lv.off, cell + 1, LB1);
             }
             Bd = tent_fma(x - fl, b0, b1);
-            const double psi0 = fabs(c0 * Bd) * ig;
-            double lim = psi_max;
-            while (psi0 > lim && k < kmax) {
-                ++k;
-                lim = lim * 4.0;
-            }
-            clamped = psi0 > lim;
-            ktrace_put(a, kt_u, n, int8_t(k));
+            psi0 = fabs(c0 * Bd) * ig;
         }
-        cnt.clamps += __popcll(__ballot(clamped));
+        if (__any(live && psi0 > psi_max)) {      // some lane sub-cycles
+            if (live) {
+                double lim = psi_max;
+                while (psi0 > lim && k < kmax) {
+                    ++k;
+                    lim = lim * 4.0;
+                }
+                clamped = psi0 > lim;
+            }
+            cnt.clamps += __popcll(__ballot(clamped));
+        }
+        if (tracing && live) ktrace_put(a, kt_u, n, int8_t(k));
         const bool heavy = live && k > 0;
 
         // A sub-cycled step outside the step-ahead window stages its own.
@@ -346,6 +360,9 @@ __global__ void __launch_bounds__(64 * WPG) push_fast_kernel(PushArgs a)
             wlo = nlo;
         }
         win = pf_next;
+#pragma unroll
+        for (int j = 0; j <= P; ++j) lvo[j] = lvo[j + 1];
+        lvo[P + 1] = lvo[P] + ncells == ring_end ? 0 : lvo[P] + ncells;
     }
     if (mine) {
         if (moved) {
