@@ -141,6 +141,7 @@ __global__ void __launch_bounds__(64 * WPG) push_fast_kernel(PushArgs a)
     const int32_t slot0 = int32_t(mod_floor(n0 - P, D));
     const double ncm1 = double(ncells - 1);
     const double c0 = 0.5 * qm * dt;
+    const double q4 = 0.25 * qm * dt;
     const HalfStepB<P> LB1;                            // B weights at s = 1/2
     const int rad = (PF_NW - 2 * margin - 4) / 2;      // cell spread the window allows
     WaveCounts cnt;
@@ -150,6 +151,7 @@ __global__ void __launch_bounds__(64 * WPG) push_fast_kernel(PushArgs a)
     const bool mine = s - p_off < np;
     double x = 0, px = 0, py = 0, pz = 0, onepz = 1, ig = 1;   // x in node units
     int kold = 0;
+    double fold = 1.0;               // dt*_old / dt
     uint8_t status = PIC_PARTICLE_LOST;
     int64_t kt_u = -1;
     if (mine) {
@@ -160,6 +162,7 @@ __global__ void __launch_bounds__(64 * WPG) push_fast_kernel(PushArgs a)
         onepz = fma(pz, pz, 1.0);
         ig = rsq_1nr(fma(px, px, fma(py, py, onepz)));
         kold = a.kold[s];
+        fold = kold < 0 ? -1.0 : ldexp(1.0, -2 * kold);
         status = a.status[s];
         if (a.ktrace) {
             const int64_t u = a.perm[s] - a.kt_first;
@@ -171,6 +174,11 @@ __global__ void __launch_bounds__(64 * WPG) push_fast_kernel(PushArgs a)
     bool win = false;        // LDS holds this step's levels on nodes [wlo, wlo + PF_NW)
     int wlo = 0;
     double pf[NPF];
+    // this lane's share of the window: field (lane bit 4), level pair (bit
+    // 5), node (bits 0..3); where it goes in LDS
+    const gdptr pf_src = (lane & 16) ? ringB : ringE;
+    const int pf_q = lane & (PF_NW - 1);
+    double *const pf_dst = sw + (lane >> 4) * WWIN + pf_q;
 
     // ring offsets of levels n - P .. n + 1 (scalar registers), moved on by
     // one slot per step
@@ -213,10 +221,9 @@ __global__ void __launch_bounds__(64 * WPG) push_fast_kernel(PushArgs a)
                 // value e = lane + 64 h: row e / 16 (level e / 32, field
                 // (e / 16) & 1), node nlo + e % 16
                 if (lane + 64 * h < ROWS * PF_NW) {
-                    const int node = min(max(nlo + (lane & (PF_NW - 1)), 0), ncells - 1);
+                    const int node = min(max(nlo + pf_q, 0), ncells - 1);
                     const int32_t off = (lane & 32) ? ln.off[2 * h + 1] : ln.off[2 * h];
-                    const gdptr src = (lane & 16) ? ringB : ringE;
-                    pf[h] = src[off + node];
+                    pf[h] = pf_src[off + node];
                 }
             }
         }
@@ -282,12 +289,14 @@ __global__ void __launch_bounds__(64 * WPG) push_fast_kernel(PushArgs a)
         bool done = false;
         if (live) {
             moved = true;
-            const int ko = kold < 0 ? k : kold;
             kold = k;
-            const double dt_new = ldexp(dt, -2 * k);
-            const double dt_old = ldexp(dt, -2 * ko);
-            const double rdx = ldexp(dtdx, -2 * k);
-            const double c1 = 0.25 * qm * (dt_old + dt_new);   // c of the transition push
+            // dt*_new / dt and dt*_old / dt (negative: cold start, p lags
+            // x by half of this step's sub-step)
+            const double fnew = ldexp(1.0, -2 * k);
+            const double c1 = q4 * ((fold < 0.0 ? fnew : fold) + fnew);   // transition push
+            fold = fnew;
+            const double rdx = dtdx * fnew;
+            const double dt_new = dt * fnew;
             if (k == 0) {
                 // s = 1/2 is the time of level n: E's weights are (0, .., 0, 1)
                 const double uE = x - 0.5;
@@ -354,7 +363,7 @@ __global__ void __launch_bounds__(64 * WPG) push_fast_kernel(PushArgs a)
 #pragma unroll
             for (int h = 0; h < NPF; ++h) {
                 const int e = lane + 64 * h;
-                if (e < ROWS * PF_NW) sw[(e / PF_NW) * WWIN + e % PF_NW] = pf[h];
+                if (e < ROWS * PF_NW) pf_dst[4 * h * WWIN] = pf[h];
             }
             wave_lds_sync();
             wlo = nlo;
