@@ -101,7 +101,9 @@ def cpu_baseline(wl, every: int, threads: int):
 
 
 class Pass:
-    """One configuration of the hot path on one workload."""
+    """One configuration of the hot path on one workload (a single run,
+    host-driven launches of S steps) or on a batch of runs (device-driven
+    windows of S steps, each run stopping at its own step count)."""
 
     def __init__(self, wl, S, precision, binning, predictor=None):
         from paper_2102_10983_amd import runner
@@ -109,16 +111,38 @@ class Pass:
         self.S = S
         self.binning = binning
         self.predictor = predictor
+        self.pb_width = 0.0625
         kernel_binning = "ballot" if binning == "ballot" else "none"
-        self.run = runner.DeviceRun(wl, S=S, precision=precision, binning=kernel_binning)
+        self.batch = isinstance(wl, list)
+        if self.batch:
+            self.run = runner.BatchRun(wl, S=S, precision=precision, binning=kernel_binning)
+            self.pusher = self.run.pusher
+            self.a0 = [w.a0 for w in wl]
+        else:
+            self.run = runner.DeviceRun(wl, S=S, precision=precision, binning=kernel_binning)
+            self.pusher = self.run.pusher
+            self.a0 = wl.a0
 
     def step(self, stream=None, events=None):
         import torch
         run, wl = self.run, self.wl
         run.reset()
-        run.pusher.counters_reset()
+        self.pusher.counters_reset()
         if self.binning == "learned":
-            self.predictor.prebin(run.pusher, wl.a0, n=0)
+            self.predictor.prebin(self.pusher, self.a0, n=None if self.batch else 0,
+                                  width=self.pb_width)
+        if self.batch:
+            for _ in range(run.windows):
+                if events is not None:
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                    self.pusher.advance(self.S)
+                    e1.record(stream)
+                    events.append((e0, e1))
+                else:
+                    self.pusher.advance(self.S)
+            return
         while run.n < wl.steps:
             s = min(self.S, wl.steps - run.n)
             run.pusher.fields_load_lattice(run.n, s, run.table, run.M, run.coeffs)
@@ -153,13 +177,20 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="large", choices=("large", "batch", "stress"),
+                    help="large: the default single run; batch: 64 uneven runs; stress: "
+                         "thermal electrons over 200 wavelengths")
     ap.add_argument("--seed", type=int, default=22, choices=(20, 21, 22))
+    ap.add_argument("--psi", type=float, default=0.01, help="psi_max of the stress workload")
     ap.add_argument("--S", type=int, default=0,
                     help="steps of dt per push launch (0: the whole run in one launch)")
     ap.add_argument("--precision", default="fp64fast", choices=("fp64", "fp32c", "fp64fast"))
     ap.add_argument("--binning", default="learned", choices=("none", "ballot", "learned"))
-    ap.add_argument("--num", type=int, default=1 << 20)
+    ap.add_argument("--num", type=int, default=0,
+                    help="electrons (large: 2^20, stress: 2^24; batch: scale factor x 1e6)")
     ap.add_argument("--periods", type=float, default=100.0)
+    ap.add_argument("--pb-width", type=float, default=0.0625,
+                    help="cost step (log2 sub-steps) of the learned group order")
     ap.add_argument("--cpu-every", type=int, default=8)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-compare", action="store_true",
@@ -186,15 +217,32 @@ def main():
     import torch
     from paper_2102_10983_amd import predictor as PR, workloads as W
 
-    wl = W.large_case(seed=args.seed, num=args.num, periods=args.periods)
-    S = wl.steps if args.S <= 0 else args.S
+    if args.workload == "large":
+        wl = W.large_case(seed=args.seed, num=args.num or (1 << 20), periods=args.periods)
+        steps_max = wl.steps
+        wdesc = (f"plane wave a0={wl.a0:g}, {wl.num} electrons at rest over 8 lambda, T/dt=75, "
+                 f"dx=1.01 c dt, {wl.ncells} cells, {wl.steps} steps, order {wl.order}, "
+                 f"psi_max {wl.psi_max}")
+    elif args.workload == "stress":
+        wl = W.stress_case(psi_max=args.psi, num=args.num or (1 << 24), periods=args.periods)
+        steps_max = wl.steps
+        wdesc = (f"plane wave a0=150, {wl.num} thermal (10 keV) electrons over 200 lambda, "
+                 f"T/dt=75, {wl.ncells} cells, {wl.steps} steps, order 3, psi_max {wl.psi_max}")
+    else:
+        scale = (args.num / 1e6) if args.num else 1.0
+        wl = W.batch_case(seed=3, nruns=64, periods=50.0, scale=scale)
+        steps_max = max(w.steps for w in wl)
+        wdesc = (f"64 runs, {sum(w.num for w in wl)} electrons (log-uniform 1e3..4e6 per run), "
+                 f"a0 log-uniform 1..150, T/dt in {{40,75,150}}, 50 periods, order 3, psi_max 0.01")
+    S = steps_max if args.S <= 0 else args.S
     model = PR.Predictor.load() if args.binning == "learned" else None
     stream = torch.cuda.current_stream()
 
     main_pass = Pass(wl, S, args.precision, args.binning, model)
+    main_pass.pb_width = args.pb_width
     events = []
     elapsed = main_pass.time(args.steps, args.warmup, stream, events)
-    counters = main_pass.run.pusher.counters()          # the last pass
+    counters = main_pass.pusher.counters()              # the last pass
     main_pass.close()
 
     sub_per_step = counters["sub_steps"]
@@ -202,10 +250,11 @@ def main():
     kernel_ms = sum(a.elapsed_time(b) for a, b in events)
     launches = len(events)
     launches_per_step = launches // args.steps
-    flops_step = algorithmic_flops(counters, wl.order)
+    order = wl[0].order if isinstance(wl, list) else wl.order
+    flops_step = algorithmic_flops(counters, order)
     achieved = flops_step * args.steps / (kernel_ms / 1e3) / 1e12
     key = "ballot" if args.binning == "ballot" else args.precision
-    traffic = measured_traffic(key, launches_per_step)
+    traffic = measured_traffic(key, launches_per_step) if args.workload == "large" else None
 
     compare = []
     if not args.no_compare:
@@ -215,7 +264,7 @@ def main():
                 continue
             p = Pass(wl, S, prec, binning)
             t = p.time(args.steps, args.warmup, stream)
-            c = p.run.pusher.counters()
+            c = p.pusher.counters()
             p.close()
             compare.append({"label": label, "precision": prec, "binning": binning,
                             "ms_per_step": t / args.steps * 1e3,
@@ -236,9 +285,7 @@ def main():
         "vs_baseline": None,
         "dtype": {"fp64": "f64", "fp64fast": "f64", "fp32c": "f32+f64"}[args.precision],
         "data": "synthetic",
-        "config": {"workload": f"plane wave a0={wl.a0:g}, {wl.num} electrons at rest over 8 "
-                               f"lambda, T/dt=75, dx=1.01 c dt, {wl.ncells} cells, {wl.steps} "
-                               f"steps, order {wl.order}, psi_max {wl.psi_max}",
+        "config": {"workload": wdesc,
                    "precision": args.precision, "binning": args.binning,
                    "steps_per_launch": S, "sub_steps_per_pass": sub_per_step,
                    "mean_sub_steps_per_particle_step": sub_per_step / counters["steps"],
@@ -250,7 +297,7 @@ def main():
                      "avg_launch_ms": kernel_ms / launches,
                      "flops_per_launch": flops_step * args.steps / launches},
     }
-    if not args.no_cpu:
+    if not args.no_cpu and args.workload == "large":
         threads = len(os.sched_getaffinity(0))
         res["cpu_baseline"] = cpu_baseline(wl, args.cpu_every, threads)
     print(json.dumps(res))

@@ -332,9 +332,11 @@ pic_status pic_mlp_adam(float *w, float *m, float *v, const float *grad, int32_t
  * index] (device, FP32, larger = more sub-steps; NaN = lightest) is cut
  * into nbuckets buckets of the given width below the largest score, and
  * each run's slots are re-filled bucket by bucket (heaviest first), in
- * position order inside a bucket.  Then the groups are started heaviest
- * first (by the largest score of their lanes) and the prio_groups
- * heaviest issue at raised priority.  Particles stay in their run;
+ * position order inside a bucket (the bins of the load-time sort).  Then the groups are started heaviest
+ * first by the largest score of their lanes, cut into steps of the same
+ * width (groups within one step keep their slot order, which keeps
+ * co-running groups close in space), and the prio_groups heaviest issue
+ * at raised priority.  Particles stay in their run;
  * results are unchanged.  Not allowed while a graph is captured
  * (PIC_E_STATE).  Synchronous. */
 pic_status pic_prebin(pic_ctx *ctx, const float *score, int32_t nbuckets, float width,

@@ -275,14 +275,37 @@ __global__ void features_kernel(FeatArgs f)
     }
 }
 
+// Largest non-NaN score (-1e30 if none): each block reduces a grid-stride
+// share into out[blockIdx.x]; a second one-block launch over those
+// partial results leaves the maximum in out[0].
+constexpr int SCORE_MAX_BLOCKS = 256;
+
+__global__ void __launch_bounds__(256) score_max_kernel(const float *in, int64_t n, float *out)
+{
+    __shared__ float part[4];
+    float m = -1e30f;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * blockDim.x) {
+        const float v = in[i];
+        if (v == v) m = fmaxf(m, v);
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        out[blockIdx.x] = fmaxf(fmaxf(part[0], part[1]), fmaxf(part[2], part[3]));
+}
+
 // Re-binning key: (run, predicted-cost bucket with heavy first, position).
 __global__ void prebin_key_kernel(const RunDesc *__restrict__ runs,
                                   const int32_t *__restrict__ group_run, const double *__restrict__ x,
                                   const int32_t *__restrict__ perm, const float *__restrict__ score,
                                   const int64_t *__restrict__ bin_off, int nbuckets, float width,
-                                  float top, int sort_sub, int64_t slots, int32_t *__restrict__ key,
-                                  int32_t *__restrict__ hist)
+                                  const float *__restrict__ topp, int sort_sub, int64_t slots,
+                                  int32_t *__restrict__ key, int32_t *__restrict__ hist)
 {
+    const float top = *topp;
     for (int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; s < slots;
          s += int64_t(gridDim.x) * blockDim.x) {
         const int32_t u = perm[s];

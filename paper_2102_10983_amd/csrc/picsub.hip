@@ -1090,7 +1090,7 @@ pic_status pic_prebin(pic_ctx *ctx, const float *score, int32_t nbuckets, float 
     if (ctx->np == 0) return PIC_OK;
     const int64_t slots = ctx->slots;
     const size_t n = size_t(slots);
-    const int psub = 4;      // position bins per cell inside a bucket
+    const int psub = ctx->tune.sort_sub;   // position bins per cell inside a bucket, as at load
     // key space: run-major, then bucket, then position
     std::vector<int64_t> bin_off(size_t(ctx->nruns)), shift(size_t(ctx->nruns));
     int64_t nb = 0;
@@ -1102,67 +1102,71 @@ pic_status pic_prebin(pic_ctx *ctx, const float *score, int32_t nbuckets, float 
     }
     if (nb >= INT32_MAX) return fail(ctx, PIC_E_ARG, "too many re-binning bins");
     const int64_t nchunks = (nb + SCAN_CHUNK - 1) / SCAN_CHUNK;
-    // top of the score range (max over particles) fixes bucket 0
-    std::vector<float> hs(size_t(ctx->np));
-    HIP_TRY(ctx, hipMemcpyAsync(hs.data(), score, hs.size() * 4, hipMemcpyDeviceToHost, ctx->stream));
-    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-    float top = -1e30f;
-    for (float v : hs)
-        if (v == v) top = std::max(top, v);
+    const bool resort = nbuckets > 1;      // one bucket: the load-time order stays
     int32_t *key = nullptr, *hist = nullptr, *sums = nullptr, *dest = nullptr, *nperm = nullptr;
     int64_t *dbin = nullptr, *dshift = nullptr;
     double *nsoa = nullptr;
     int8_t *nk = nullptr;
     uint8_t *nst = nullptr;
-    float *gcost = nullptr;
+    float *gcost = nullptr, *top = nullptr;
     pic_status st = PIC_OK;
     hipError_t e = hipSuccess;
     std::vector<float> hg;
     std::vector<int32_t> order;
     std::vector<int8_t> prio;
-    if ((st = dev_alloc(ctx, &key, n)) || (st = dev_alloc(ctx, &hist, size_t(nb))) ||
-        (st = dev_alloc(ctx, &sums, size_t(nchunks))) || (st = dev_alloc(ctx, &dest, n)) ||
-        (st = dev_alloc(ctx, &nperm, n)) || (st = dev_alloc(ctx, &dbin, bin_off.size())) ||
-        (st = dev_alloc(ctx, &dshift, shift.size())) || (st = dev_alloc(ctx, &nsoa, 4 * n)) ||
-        (st = dev_alloc(ctx, &nk, n)) || (st = dev_alloc(ctx, &nst, n)) ||
-        (st = dev_alloc(ctx, &gcost, size_t(ctx->ngroups))))
+    if ((st = dev_alloc(ctx, &gcost, size_t(ctx->ngroups)))) goto out;
+    if (resort &&
+        ((st = dev_alloc(ctx, &key, n)) || (st = dev_alloc(ctx, &hist, size_t(nb))) ||
+         (st = dev_alloc(ctx, &sums, size_t(nchunks))) || (st = dev_alloc(ctx, &dest, n)) ||
+         (st = dev_alloc(ctx, &nperm, n)) || (st = dev_alloc(ctx, &dbin, bin_off.size())) ||
+         (st = dev_alloc(ctx, &dshift, shift.size())) || (st = dev_alloc(ctx, &nsoa, 4 * n)) ||
+         (st = dev_alloc(ctx, &nk, n)) || (st = dev_alloc(ctx, &nst, n)) ||
+         (st = dev_alloc(ctx, &top, size_t(SCORE_MAX_BLOCKS)))))
         goto out;
-    e = hipMemcpyAsync(dbin, bin_off.data(), bin_off.size() * 8, hipMemcpyHostToDevice, ctx->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(dshift, shift.data(), shift.size() * 8, hipMemcpyHostToDevice, ctx->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(hist, 0, size_t(nb) * 4, ctx->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(nperm, 0xFF, n * 4, ctx->stream);
-    // padding slots keep their contents: start the new arrays as copies
-    {
+    if (resort) {
+        e = hipMemcpyAsync(dbin, bin_off.data(), bin_off.size() * 8, hipMemcpyHostToDevice,
+                           ctx->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(dshift, shift.data(), shift.size() * 8, hipMemcpyHostToDevice,
+                               ctx->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(hist, 0, size_t(nb) * 4, ctx->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(nperm, 0xFF, n * 4, ctx->stream);
+        // padding slots keep their contents: start the new arrays as copies
         const double *soa[4] = {ctx->x, ctx->px, ctx->py, ctx->pz};
         for (int a = 0; a < 4 && e == hipSuccess; ++a)
             e = hipMemcpyAsync(nsoa + a * n, soa[a], n * 8, hipMemcpyDeviceToDevice, ctx->stream);
-    }
-    if (e == hipSuccess) e = hipMemcpyAsync(nk, ctx->kold, n, hipMemcpyDeviceToDevice, ctx->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(nst, ctx->status, n, hipMemcpyDeviceToDevice, ctx->stream);
-    if (e == hipSuccess) {
-        const int g = grid_for(slots, 256, 8192);
-        prebin_key_kernel<<<g, 256, 0, ctx->stream>>>(ctx->d_runs, ctx->group_run, ctx->x,
-                                                      ctx->perm, score, dbin, nbuckets, width, top,
-                                                      psub, slots, key, hist);
-        scan_sums_kernel<<<unsigned(nchunks), 256, 0, ctx->stream>>>(hist, nb, sums);
-        scan_top_kernel<<<1, 1024, 0, ctx->stream>>>(sums, int(nchunks));
-        scan_chunk_kernel<<<unsigned(nchunks), 256, 0, ctx->stream>>>(hist, nb, sums);
-        prebin_scatter_kernel<<<g, 256, 0, ctx->stream>>>(key, ctx->perm, ctx->group_run, dshift,
-                                                          slots, hist, dest);
-        permute_state_kernel<<<g, 256, 0, ctx->stream>>>(
-            dest, slots, ctx->x, ctx->px, ctx->py, ctx->pz, ctx->kold, ctx->status, ctx->perm,
-            nsoa, nsoa + n, nsoa + 2 * n, nsoa + 3 * n, nk, nst, nperm);
-        e = hipGetLastError();
-    }
-    {
-        double *soa[4] = {ctx->x, ctx->px, ctx->py, ctx->pz};
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(nk, ctx->kold, n, hipMemcpyDeviceToDevice, ctx->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(nst, ctx->status, n, hipMemcpyDeviceToDevice, ctx->stream);
+        if (e == hipSuccess) {
+            // top of the score range (max over particles) fixes bucket 0
+            score_max_kernel<<<SCORE_MAX_BLOCKS, 256, 0, ctx->stream>>>(score, ctx->np, top);
+            score_max_kernel<<<1, 256, 0, ctx->stream>>>(top, SCORE_MAX_BLOCKS, top);
+            const int g = grid_for(slots, 256, 8192);
+            prebin_key_kernel<<<g, 256, 0, ctx->stream>>>(ctx->d_runs, ctx->group_run, ctx->x,
+                                                          ctx->perm, score, dbin, nbuckets, width,
+                                                          top, psub, slots, key, hist);
+            scan_sums_kernel<<<unsigned(nchunks), 256, 0, ctx->stream>>>(hist, nb, sums);
+            scan_top_kernel<<<1, 1024, 0, ctx->stream>>>(sums, int(nchunks));
+            scan_chunk_kernel<<<unsigned(nchunks), 256, 0, ctx->stream>>>(hist, nb, sums);
+            prebin_scatter_kernel<<<g, 256, 0, ctx->stream>>>(key, ctx->perm, ctx->group_run,
+                                                              dshift, slots, hist, dest);
+            permute_state_kernel<<<g, 256, 0, ctx->stream>>>(
+                dest, slots, ctx->x, ctx->px, ctx->py, ctx->pz, ctx->kold, ctx->status, ctx->perm,
+                nsoa, nsoa + n, nsoa + 2 * n, nsoa + 3 * n, nk, nst, nperm);
+            e = hipGetLastError();
+        }
+        double *soa2[4] = {ctx->x, ctx->px, ctx->py, ctx->pz};
         for (int a = 0; a < 4 && e == hipSuccess; ++a)
-            e = hipMemcpyAsync(soa[a], nsoa + a * n, n * 8, hipMemcpyDeviceToDevice, ctx->stream);
+            e = hipMemcpyAsync(soa2[a], nsoa + a * n, n * 8, hipMemcpyDeviceToDevice, ctx->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(ctx->kold, nk, n, hipMemcpyDeviceToDevice, ctx->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(ctx->perm, nperm, n * 4, hipMemcpyDeviceToDevice, ctx->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(ctx->status, nst, n, hipMemcpyDeviceToDevice, ctx->stream);
     }
-    if (e == hipSuccess) e = hipMemcpyAsync(ctx->kold, nk, n, hipMemcpyDeviceToDevice, ctx->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(ctx->perm, nperm, n * 4, hipMemcpyDeviceToDevice, ctx->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(ctx->status, nst, n, hipMemcpyDeviceToDevice, ctx->stream);
     // dispatch order: groups by predicted cost, heaviest first; raised
     // priority for the prio_groups heaviest
     if (e == hipSuccess) {
@@ -1178,8 +1182,17 @@ pic_status pic_prebin(pic_ctx *ctx, const float *score, int32_t nbuckets, float 
     if (e == hipSuccess) {
         order.resize(hg.size());
         std::iota(order.begin(), order.end(), 0);
+        // heaviest first, in steps of `width`: groups of one cost step keep
+        // their slot (position, run) order, so waves that run together still
+        // share field data in the caches
+        float gtop = -1e30f;
+        for (float v : hg) gtop = std::max(gtop, v);
+        std::vector<int32_t> gb(hg.size());
+        for (size_t g = 0; g < hg.size(); ++g)
+            gb[g] = hg[g] > -1e29f ? int32_t(std::min(std::floor((gtop - hg[g]) / width), 1e9f))
+                                   : INT32_MAX;
         std::stable_sort(order.begin(), order.end(),
-                         [&](int32_t a, int32_t b) { return hg[size_t(a)] > hg[size_t(b)]; });
+                         [&](int32_t a, int32_t b) { return gb[size_t(a)] < gb[size_t(b)]; });
         prio.assign(hg.size(), 0);
         for (int32_t i = 0; i < std::min<int32_t>(prio_groups, ctx->ngroups); ++i)
             if (hg[size_t(order[size_t(i)])] > -1e29f) prio[size_t(order[size_t(i)])] = 1;
@@ -1193,7 +1206,7 @@ pic_status pic_prebin(pic_ctx *ctx, const float *score, int32_t nbuckets, float 
     if (e != hipSuccess) st = fail(ctx, PIC_E_DEVICE, "prebin: %s", hipGetErrorString(e));
 out:
     (void)hipStreamSynchronize(ctx->stream);
-    void *tmps[] = {key, hist, sums, dest, nperm, dbin, dshift, nsoa, nk, nst, gcost};
+    void *tmps[] = {key, hist, sums, dest, nperm, dbin, dshift, nsoa, nk, nst, gcost, top};
     for (void *p : tmps)
         if (p) (void)hipFree(p);
     return st;

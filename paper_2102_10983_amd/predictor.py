@@ -79,7 +79,7 @@ class Predictor:
         """Predicted log2 load of every particle of `pusher` at level n."""
         return self.predict(pusher.features(a0, n=n))
 
-    def prebin(self, pusher: picsub.Pusher, a0, n=None, nbuckets: int = 1, width: float = 0.25,
+    def prebin(self, pusher: picsub.Pusher, a0, n=None, nbuckets: int = 1, width: float = 0.0625,
                prio_groups: int = 0):
         """Score the particles and re-bin / re-order the groups."""
         s = self.score(pusher, a0, n)
