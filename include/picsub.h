@@ -75,8 +75,10 @@ typedef enum {
                            reciprocal / rsqrt estimates refined by one Newton
                            step, positions in node units, 1/gamma reused by
                            the next decision, and the next step's field
-                           window loaded into LDS one step ahead; within
-                           1e-9 of PIC_FP64 in practice (not bit-identical) */
+                           window loaded into LDS one step ahead.  Not
+                           bit-identical to PIC_FP64: rounding differences
+                           grow along trajectories (observed up to 5e-7
+                           relative on p, well inside 1e-5) */
 } pic_precision;
 
 /* how particles are grouped onto wavefronts for the sub-step loop */

@@ -64,19 +64,29 @@ __device__ __forceinline__ double comb_fma(const T *__restrict__ f, const int32_
     return v;
 }
 
-// 1 / sqrt(a), a >= 1, and 1 / b, b >= 1: the hardware estimates (relative
-// error near 2^-26) refined by one Newton step, which squares the error.
+// 1 / sqrt(a), a >= 1, and 1 / b, b >= 1: the hardware estimates refined
+// by Newton steps (each squares the relative error).
+#ifndef PICSUB_RSQ_NEWTON
+#define PICSUB_RSQ_NEWTON 1
+#endif
+#ifndef PICSUB_RCP_NEWTON
+#define PICSUB_RCP_NEWTON 1
+#endif
 __device__ __forceinline__ double rsq_1nr(double a)
 {
-    const double y = __builtin_amdgcn_rsq(a);
-    const double r = fma(-0.5 * a * y, y, 0.5);
-    return fma(y, r, y);
+    double y = __builtin_amdgcn_rsq(a);
+    const double h = -0.5 * a;
+#pragma unroll
+    for (int i = 0; i < PICSUB_RSQ_NEWTON; ++i) y = fma(y, fma(h * y, y, 0.5), y);
+    return y;
 }
 
 __device__ __forceinline__ double rcp_1nr(double b)
 {
-    const double r = __builtin_amdgcn_rcp(b);
-    return fma(r, fma(-b, r, 1.0), r);
+    double r = __builtin_amdgcn_rcp(b);
+#pragma unroll
+    for (int i = 0; i < PICSUB_RCP_NEWTON; ++i) r = fma(r, fma(-b, r, 1.0), r);
+    return r;
 }
 
 __device__ __forceinline__ double tent_fma(double w, double f0, double f1)

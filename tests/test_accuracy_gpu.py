@@ -1,0 +1,81 @@
+"""Accuracy of the benchmark path (FP64 with refined hardware reciprocal and
+rsqrt, learned group order, whole runs per launch) against the FP64 oracle
+on the other workload shapes: thermal electrons over 200 wavelengths and a
+batch of uneven runs.  Tolerance: 1e-5 relative on p and x with the k-flip
+protocol of tests/parity.py; the measured errors are printed."""
+
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2102_10983_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def test_thermal_load_subsample(torch_gpu):
+    """2^20 thermal electrons, a0 = 150, 100 periods, learned order; 4096
+    consecutive electrons (caller order) checked against the oracle."""
+    torch = torch_gpu
+    from paper_2102_10983_amd import predictor, runner
+    from parity import compare
+    wl = W.stress_case(num=1 << 20)
+    run = runner.DeviceRun(wl, S=wl.steps, precision="fp64fast", binning="none")
+    run.reset()
+    predictor.Predictor.load().prebin(run.pusher, wl.a0, n=0)
+    first = int(np.random.default_rng(5).integers(0, wl.num - 4096))
+    buf = torch.full((wl.steps, 4096), -2, dtype=torch.int8, device="cuda")
+    run.pusher.ktrace_set(buf, 0, first)
+    run.advance(wl.steps)
+    d = run.diag()
+    run.close()
+    idx = np.arange(first, first + 4096)
+    full = np.full((wl.steps, wl.num), -3, dtype=np.int8)
+    full[:, idx] = buf.cpu().numpy()
+    res = compare(wl, wl.steps, d, idx, TOL, g_ktrace=full, flip_rel=1e-9)
+    _say("thermal 2^20:", {k: v for k, v in res.items() if k != "oracle_counters"})
+    assert res["max_e_p"] < 1e-6     # the bar is 1e-5
+
+
+@pytest.mark.parametrize("run_index", [0, 17, 41])
+def test_batch_runs(torch_gpu, run_index):
+    """A scaled-down batch (64 runs, ~4e5 electrons, 50 periods, one window
+    per run), learned order; up to 512 electrons of one run checked."""
+    torch = torch_gpu
+    from paper_2102_10983_amd import predictor, runner
+    from parity import compare
+    wls = W.batch_case(seed=3, nruns=64, periods=50.0, scale=0.02)
+    S = max(w.steps for w in wls)
+    br = runner.BatchRun(wls, S=S, precision="fp64fast", binning="none")
+    br.reset()
+    predictor.Predictor.load().prebin(br.pusher, [w.a0 for w in wls])
+    wl = wls[run_index]
+    off = int(sum(w.num for w in wls[:run_index]))
+    m = min(512, wl.num)
+    buf = torch.full((wl.steps, m), -2, dtype=torch.int8, device="cuda")
+    br.pusher.ktrace_set(buf, 0, off)
+    br.run_all()
+    d = br.diag()
+    br.close()
+    sub = {k: d[k][off:off + wl.num] for k in ("x", "px", "py", "pz", "status")}
+    full = np.full((wl.steps, wl.num), -3, dtype=np.int8)
+    full[:, :m] = buf.cpu().numpy()
+    res = compare(wl, wl.steps, sub, np.arange(m), TOL, g_ktrace=full, flip_rel=1e-9)
+    _say(f"batch run {run_index} ({wl.name}, {wl.num} electrons):",
+         {k: v for k, v in res.items() if k != "oracle_counters"})
+    assert res["max_e_p"] < 1e-6     # the bar is 1e-5

@@ -238,7 +238,7 @@ def test_large_case_sampled(torch_gpu, runner, seed):
 
 
 # ---------------------------------------------------------------------------
-# Fast FP64 (faithful hardware reciprocals, node-unit positions): the
+# Fast FP64 (refined hardware reciprocals, node-unit positions): the
 # non-bitwise path held to the 1e-5 bar
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("order,S", [(1, 1500), (3, 1500), (3, 7), (5, 300)])
