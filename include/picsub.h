@@ -276,6 +276,28 @@ int32_t pic_group_count(const pic_ctx *ctx);
 pic_status pic_order_set(pic_ctx *ctx, const int32_t *order, pic_mem mem);
 
 /* ------------------------------------------------------------------
+ * Checkpoint (not part of the paper): the state the library owns and the
+ * caller cannot rebuild — every particle's x, p, k_last and status (caller
+ * order), the counters of every run and each run's device-driven level —
+ * in one host buffer.  Field levels are not included: after an import the
+ * caller loads the levels the next push needs (pic_fields_load*, or
+ * pic_source_set with n_start = the returned level).
+ * ------------------------------------------------------------------ */
+
+/* buf == NULL: *bytes = the size needed.  Otherwise writes the checkpoint
+ * into buf (host memory, *bytes at least that size; any alignment) and
+ * sets *bytes to the size written.  Synchronises the stream. */
+pic_status pic_state_export(pic_ctx *ctx, void *buf, size_t *bytes);
+
+/* Restore a checkpoint written by pic_state_export from a context with
+ * the same runs (particle counts, ncells, order; PIC_E_ARG otherwise):
+ * particles (re-sorted by position), status flags and counters.  levels
+ * (host array of nruns, may be NULL) receives each run's recorded
+ * device-driven level.  The group order and priorities are reset.
+ * Synchronises the stream. */
+pic_status pic_state_import(pic_ctx *ctx, const void *buf, size_t bytes, int64_t *levels);
+
+/* ------------------------------------------------------------------
  * Learned load predictor.
  *
  * Not part of the paper's method: the paper decides k from Psi alone

@@ -501,18 +501,24 @@ const char *pic_last_error(const pic_ctx *ctx)
     return ctx ? ctx->err : "null context";
 }
 
-pic_status pic_particles_set(pic_ctx *ctx, pic_mem mem, const double *x, const double *px,
-                             const double *py, const double *pz, const int8_t *k_old)
+namespace {
+// Load the particle state (caller order, host or device arrays), sort it
+// into slots by (run, position bin) and reset counters and group order.
+// status may be NULL (every particle live).
+pic_status load_particles(pic_ctx *ctx, pic_mem mem, const double *x, const double *px,
+                          const double *py, const double *pz, const int8_t *k_old,
+                          const uint8_t *status)
 {
-    CTX_CHECK(ctx);
     const int64_t np = ctx->np;
     if (np > 0 && (!x || !px || !py || !pz)) return fail(ctx, PIC_E_ARG, "null particle array");
     if (mem != PIC_MEM_HOST && mem != PIC_MEM_DEVICE) return fail(ctx, PIC_E_ARG, "bad pic_mem");
     const size_t n = size_t(np);
     const double *dx_ = x, *dpx = px, *dpy = py, *dpz = pz;
     const int8_t *dk = k_old;
+    const uint8_t *dst = status;
     double *tmp = nullptr;
     int8_t *tmpk = nullptr;
+    uint8_t *tmps_ = nullptr;
     int32_t *hist = nullptr, *sums = nullptr;
     LoadRun *dlr = nullptr;
     pic_status result = PIC_OK;
@@ -521,8 +527,10 @@ pic_status pic_particles_set(pic_ctx *ctx, pic_mem mem, const double *x, const d
     int64_t nb = 0, nchunks = 0;
     if (mem == PIC_MEM_HOST && np > 0) {
         if ((result = dev_alloc(ctx, &tmp, 4 * n))) return result;
-        if (k_old && (result = dev_alloc(ctx, &tmpk, n))) {
+        if ((k_old && (result = dev_alloc(ctx, &tmpk, n))) ||
+            (status && (result = dev_alloc(ctx, &tmps_, n)))) {
             (void)hipFree(tmp);
+            if (tmpk) (void)hipFree(tmpk);
             return result;
         }
         const double *src[4] = {x, px, py, pz};
@@ -531,6 +539,9 @@ pic_status pic_particles_set(pic_ctx *ctx, pic_mem mem, const double *x, const d
                                ctx->stream);
         if (e == hipSuccess && k_old)
             e = hipMemcpyAsync(tmpk, k_old, n, hipMemcpyHostToDevice, ctx->stream);
+        if (e == hipSuccess && status)
+            e = hipMemcpyAsync(tmps_, status, n, hipMemcpyHostToDevice, ctx->stream);
+        dst = tmps_;
         dx_ = tmp;
         dpx = tmp + n;
         dpy = tmp + 2 * n;
@@ -569,7 +580,7 @@ pic_status pic_particles_set(pic_ctx *ctx, pic_mem mem, const double *x, const d
     if (e == hipSuccess) {
         gather_state_kernel<<<grid_for(ctx->slots, 256, 8192), 256, 0, ctx->stream>>>(
             ctx->perm, ctx->slots, dx_, dpx, dpy, dpz, dk, ctx->x, ctx->px, ctx->py, ctx->pz,
-            ctx->kold, ctx->status);
+            ctx->kold, ctx->status, dst);
         e = hipGetLastError();
     }
     if (e == hipSuccess)
@@ -588,10 +599,18 @@ pic_status pic_particles_set(pic_ctx *ctx, pic_mem mem, const double *x, const d
     else ctx->have_particles = true;
 done:
     (void)hipStreamSynchronize(ctx->stream);
-    void *tmps[] = {tmp, tmpk, hist, sums, dlr};
+    void *tmps[] = {tmp, tmpk, tmps_, hist, sums, dlr};
     for (void *p : tmps)
         if (p) (void)hipFree(p);
     return result;
+}
+}  // namespace
+
+pic_status pic_particles_set(pic_ctx *ctx, pic_mem mem, const double *x, const double *px,
+                             const double *py, const double *pz, const int8_t *k_old)
+{
+    CTX_CHECK(ctx);
+    return load_particles(ctx, mem, x, px, py, pz, k_old, nullptr);
 }
 
 pic_status pic_fields_load_r(pic_ctx *ctx, int32_t run, int64_t n, pic_mem mem, const double *Ey,
@@ -1210,6 +1229,145 @@ out:
     for (void *p : tmps)
         if (p) (void)hipFree(p);
     return st;
+}
+
+
+// ---------------------------------------------------------------------
+// Checkpoint
+// ---------------------------------------------------------------------
+namespace {
+struct CkptHeader {
+    char magic[8];
+    uint32_t version;
+    int32_t nruns;
+    int64_t np;
+};
+struct CkptRun {
+    int64_t np;
+    int64_t level;
+    int32_t ncells;
+    int32_t order;
+};
+constexpr char CKPT_MAGIC[8] = {'P', 'I', 'C', 'S', 'U', 'B', 'C', 'K'};
+
+size_t ckpt_bytes(const pic_ctx *ctx)
+{
+    const size_t n = size_t(ctx->np);
+    return sizeof(CkptHeader) + size_t(ctx->nruns) * (sizeof(CkptRun) + sizeof(pic_counters)) +
+           n * (4 * sizeof(double) + 2);
+}
+}  // namespace
+
+pic_status pic_state_export(pic_ctx *ctx, void *buf, size_t *bytes)
+{
+    CTX_CHECK(ctx);
+    if (!bytes) return fail(ctx, PIC_E_ARG, "null size");
+    const size_t need = ckpt_bytes(ctx);
+    if (!buf) {
+        *bytes = need;
+        return PIC_OK;
+    }
+    if (*bytes < need) return fail(ctx, PIC_E_ARG, "buffer of %zu bytes, need %zu", *bytes, need);
+    if (!ctx->have_particles) return fail(ctx, PIC_E_STATE, "particles not loaded");
+    const size_t n = size_t(ctx->np);
+    std::vector<double> px(n), py(n), pz(n), x(n);
+    std::vector<int8_t> k(n);
+    std::vector<uint8_t> st(n);
+    pic_status s = pic_diag(ctx, PIC_MEM_HOST, nullptr, px.data(), py.data(), pz.data(), x.data(),
+                            k.data(), st.data(), nullptr);
+    if (s) return s;
+    char *o = static_cast<char *>(buf);
+    CkptHeader h{};
+    std::memcpy(h.magic, CKPT_MAGIC, 8);
+    h.version = 1;
+    h.nruns = ctx->nruns;
+    h.np = ctx->np;
+    std::memcpy(o, &h, sizeof h);
+    o += sizeof h;
+    for (int r = 0; r < ctx->nruns; ++r) {
+        const RunHost &R = ctx->runs[size_t(r)];
+        CkptRun cr{R.np, R.n_dev, R.prm.ncells, R.prm.order};
+        std::memcpy(o, &cr, sizeof cr);
+        o += sizeof cr;
+    }
+    for (int r = 0; r < ctx->nruns; ++r) {
+        pic_counters c;
+        if ((s = read_counters(ctx, r, &c))) return s;
+        std::memcpy(o, &c, sizeof c);
+        o += sizeof c;
+    }
+    const std::vector<double> *arrs[4] = {&x, &px, &py, &pz};
+    for (const auto *a : arrs) {
+        std::memcpy(o, a->data(), n * sizeof(double));
+        o += n * sizeof(double);
+    }
+    std::memcpy(o, k.data(), n);
+    o += n;
+    std::memcpy(o, st.data(), n);
+    *bytes = need;
+    return PIC_OK;
+}
+
+pic_status pic_state_import(pic_ctx *ctx, const void *buf, size_t bytes, int64_t *levels)
+{
+    CTX_CHECK(ctx);
+    if (!buf) return fail(ctx, PIC_E_ARG, "null buffer");
+    if (ctx->gexec) return fail(ctx, PIC_E_STATE, "release the captured graph before importing");
+    const size_t need = ckpt_bytes(ctx);
+    if (bytes < sizeof(CkptHeader)) return fail(ctx, PIC_E_ARG, "truncated checkpoint");
+    const char *i = static_cast<const char *>(buf);
+    CkptHeader h;
+    std::memcpy(&h, i, sizeof h);
+    i += sizeof h;
+    if (std::memcmp(h.magic, CKPT_MAGIC, 8) != 0 || h.version != 1)
+        return fail(ctx, PIC_E_ARG, "not a checkpoint of this library");
+    if (h.nruns != ctx->nruns || h.np != ctx->np || bytes < need)
+        return fail(ctx, PIC_E_ARG, "checkpoint of %d runs / %lld particles, context has %d / %lld",
+                    h.nruns, (long long)h.np, ctx->nruns, (long long)ctx->np);
+    std::vector<int64_t> lev(size_t(ctx->nruns));
+    for (int r = 0; r < ctx->nruns; ++r) {
+        CkptRun cr;
+        std::memcpy(&cr, i, sizeof cr);
+        i += sizeof cr;
+        const RunHost &R = ctx->runs[size_t(r)];
+        if (cr.np != R.np || cr.ncells != R.prm.ncells || cr.order != R.prm.order)
+            return fail(ctx, PIC_E_ARG, "run %d does not match the checkpoint", r);
+        lev[size_t(r)] = cr.level;
+    }
+    std::vector<pic_counters> cs(size_t(ctx->nruns));
+    for (auto &c : cs) {
+        std::memcpy(&c, i, sizeof c);
+        i += sizeof c;
+    }
+    const size_t n = size_t(ctx->np);
+    std::vector<double> soa(4 * n);
+    std::memcpy(soa.data(), i, 4 * n * sizeof(double));
+    i += 4 * n * sizeof(double);
+    std::vector<int8_t> k(n);
+    std::vector<uint8_t> st(n);
+    std::memcpy(k.data(), i, n);
+    i += n;
+    std::memcpy(st.data(), i, n);
+    for (uint8_t v : st)
+        if (v != PIC_PARTICLE_LIVE && v != PIC_PARTICLE_LOST)
+            return fail(ctx, PIC_E_ARG, "bad status flag in checkpoint");
+    pic_status s = load_particles(ctx, PIC_MEM_HOST, soa.data(), soa.data() + n,
+                                  soa.data() + 2 * n, soa.data() + 3 * n, k.data(), st.data());
+    if (s) return s;
+    // counters: each run's totals go to its first slot
+    std::vector<uint64_t> w(cnt_words(ctx), 0);
+    for (int r = 0; r < ctx->nruns; ++r) {
+        uint64_t *v = w.data() + size_t(r) * NSLOT * NCNT;
+        for (int kk = 0; kk < PIC_KHIST; ++kk) v[kk] = cs[size_t(r)].steps_by_k[kk];
+        v[CNT_CLAMPS] = cs[size_t(r)].clamps;
+        v[CNT_LOST] = cs[size_t(r)].lost;
+    }
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->cnt, w.data(), w.size() * sizeof(uint64_t),
+                                hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    if (levels)
+        for (int r = 0; r < ctx->nruns; ++r) levels[r] = lev[size_t(r)];
+    return PIC_OK;
 }
 
 }  // extern "C"

@@ -224,7 +224,8 @@ __global__ void gather_state_kernel(const int32_t *__restrict__ perm, int64_t sl
                                     const int8_t *__restrict__ kold, double *__restrict__ sx,
                                     double *__restrict__ spx, double *__restrict__ spy,
                                     double *__restrict__ spz, int8_t *__restrict__ skold,
-                                    uint8_t *__restrict__ sstatus)
+                                    uint8_t *__restrict__ sstatus,
+                                    const uint8_t *__restrict__ status)
 {
     for (int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; s < slots;
          s += int64_t(gridDim.x) * blockDim.x) {
@@ -235,7 +236,7 @@ __global__ void gather_state_kernel(const int32_t *__restrict__ perm, int64_t sl
             spy[s] = py[u];
             spz[s] = pz[u];
             skold[s] = kold ? kold[u] : int8_t(-1);
-            sstatus[s] = PIC_PARTICLE_LIVE;
+            sstatus[s] = status ? status[u] : uint8_t(PIC_PARTICLE_LIVE);
         } else {
             sx[s] = spx[s] = spy[s] = spz[s] = 0.0;
             skold[s] = -1;

@@ -31,7 +31,8 @@ EXPORTS = ("pic_create", "pic_destroy", "pic_last_error", "pic_particles_set",
            "pic_run_level", "pic_graph_capture", "pic_graph_launch", "pic_graph_release",
            "pic_run_counters", "pic_tune_set", "pic_tune_get", "pic_autotune",
            "pic_group_count", "pic_order_set", "pic_features", "pic_mlp_forward",
-           "pic_mlp_grad", "pic_mlp_adam", "pic_prebin")
+           "pic_mlp_grad", "pic_mlp_adam", "pic_prebin", "pic_state_export",
+           "pic_state_import")
 
 MLP_FEATURES = 8
 MLP_HIDDEN = 64
@@ -122,6 +123,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "pic_mlp_adam": ([vp, vp, vp, vp, i32, C.c_float, C.c_float, C.c_float, C.c_float, i32,
                           vp], C.c_int),
         "pic_prebin": ([vp, vp, i32, C.c_float, i32], C.c_int),
+        "pic_state_export": ([vp, vp, C.POINTER(C.c_size_t)], C.c_int),
+        "pic_state_import": ([vp, vp, C.c_size_t, vp], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -364,6 +367,20 @@ class Pusher:
         torch.cuda.current_stream().synchronize()
         self._check(self._lib.pic_prebin(self._ctx, ptr, int(nbuckets), float(width),
                                          int(prio_groups)))
+
+    def state_export(self) -> bytes:
+        """Checkpoint of the particle state, counters and run levels."""
+        n = C.c_size_t(0)
+        self._check(self._lib.pic_state_export(self._ctx, None, C.byref(n)))
+        buf = C.create_string_buffer(n.value)
+        self._check(self._lib.pic_state_export(self._ctx, buf, C.byref(n)))
+        return buf.raw[:n.value]
+
+    def state_import(self, blob: bytes):
+        """Restore a checkpoint; returns each run's recorded level."""
+        lev = np.zeros(self.nruns, dtype=np.int64)
+        self._check(self._lib.pic_state_import(self._ctx, blob, len(blob), lev.ctypes.data))
+        return lev
 
     def ktrace_set(self, buf, n_first: int = 0, first: int = 0):
         """Record k for caller indices [first, first + buf.shape[1]) at steps

@@ -155,3 +155,41 @@ def test_order_must_be_a_permutation(torch_gpu):
     with pytest.raises(picsub.PicError):
         b.pusher.order_set(np.zeros(ng, dtype=np.int32))
     b.close()
+
+
+def test_checkpoint_resume_equals_uninterrupted_run(torch_gpu):
+    """Export after half the steps, import into a fresh context, finish:
+    the same bits as the run that was never stopped (FP64), counters
+    included; a mismatched context is refused."""
+    from paper_2102_10983_amd import picsub, runner
+    wls = _small_batch(seed=13)
+    full = runner.BatchRun(wls, S=40, precision="fp64")
+    full.reset()
+    full.run_all()
+    want = full.diag()
+    full.close()
+
+    a = runner.BatchRun(wls, S=40, precision="fp64")
+    a.reset()
+    a.pusher.advance(40)
+    a.pusher.advance(40)
+    blob = a.pusher.state_export()
+    a.close()
+    b = runner.BatchRun(wls, S=40, precision="fp64")
+    b.pusher.particles_set(b.x0, *b.p0)
+    lev = b.pusher.state_import(blob)
+    assert all(lv == min(80, wl.steps) for lv, wl in zip(lev, wls))
+    for r, (wl, (tab, M, co)) in enumerate(zip(b.wls, b.tables)):
+        b.pusher.source_set(r, int(lev[r]), tab, M, co, n_stop=wl.steps)
+    for _ in range(b.windows - 2):
+        b.pusher.advance(40)
+    got = b.diag()
+    b.close()
+    assert _same(_state(got), _state(want))
+    assert got["counters"] == want["counters"]
+
+    other = runner.BatchRun(_small_batch(seed=14), S=40, precision="fp64")
+    other.reset()
+    with pytest.raises(picsub.PicError):
+        other.pusher.state_import(blob)
+    other.close()
