@@ -178,6 +178,12 @@ __device__ __forceinline__ void split(double v, float &hi, float &lo)
     lo = float(v - double(hi));
 }
 
+// Lane masks straight from the compare (no round trip through a vector
+// register): the bits of the active lanes where p holds.
+__device__ __forceinline__ uint64_t wballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+__device__ __forceinline__ bool wany(bool p) { return wballot(p) != 0; }
+__device__ __forceinline__ bool wall(bool p) { return wballot(!p) == 0; }
+
 __device__ __forceinline__ int wave_min(int v)
 {
 #pragma unroll
@@ -239,11 +245,11 @@ struct WaveCounts {
     // lanes with `done` completed a step with exponent k
     __device__ __forceinline__ void steps_done(bool done, int k)
     {
-        steps[0] += __popcll(__ballot(done && k == 0));
-        if (__any(done && k > 0)) {
+        steps[0] += __popcll(wballot(done & (k == 0)));
+        if (wany(done & (k > 0))) {
 #pragma unroll
             for (int kk = 1; kk <= PIC_K_MAX_LIMIT; ++kk)
-                steps[kk] += __popcll(__ballot(done && k == kk));
+                steps[kk] += __popcll(wballot(done & (k == kk)));
         }
     }
     __device__ __forceinline__ void flush(uint64_t *__restrict__ slot, int lane) const

@@ -188,6 +188,7 @@ __global__ void __launch_bounds__(64 * WPG) push_fast_kernel(PushArgs a)
     // 5), node (bits 0..3); where it goes in LDS
     const gdptr pf_src = (lane & 16) ? ringB : ringE;
     const int pf_q = lane & (PF_NW - 1);
+    const bool pf_hi = (lane & 32) != 0;          // odd level of each pair
     double *const pf_dst = sw + (lane >> 4) * WWIN + pf_q;
 
     // ring offsets of levels n - P .. n + 1 (scalar registers), moved on by
@@ -202,12 +203,17 @@ __global__ void __launch_bounds__(64 * WPG) push_fast_kernel(PushArgs a)
         Levels<P> lv;
 #pragma unroll
         for (int j = 0; j <= P; ++j) lv.off[j] = lvo[j];
-        const bool live = status == PIC_PARTICLE_LIVE && x >= 0.5 && x < ncm1;
-        const bool left = status == PIC_PARTICLE_LIVE && !live;
-        cnt.lost += __popcll(__ballot(left));
-        if (left) status = PIC_PARTICLE_LOST;
-        if (tracing && !live) ktrace_put(a, kt_u, n, -1);
-        const uint64_t lmask = __ballot(live);
+        // masks of compares, combined on the scalar unit
+        const uint64_t amask = wballot(status == PIC_PARTICLE_LIVE);
+        const uint64_t lmask = amask & wballot(x >= 0.5) & wballot(x < ncm1);
+        const bool live = (status == PIC_PARTICLE_LIVE) & (x >= 0.5) & (x < ncm1);
+        if (amask != lmask) {                      // some lane left the grid
+            cnt.lost += __popcll(amask & ~lmask);
+            if ((status == PIC_PARTICLE_LIVE) & !live) status = PIC_PARTICLE_LOST;
+        }
+        if (tracing) {
+            if (!live) ktrace_put(a, kt_u, n, -1);
+        }
         if (!lmask) {
             for (int s2 = st + 1; s2 < S_run; ++s2) ktrace_put(a, kt_u, n0 + s2, -1);
             break;
@@ -220,19 +226,17 @@ __global__ void __launch_bounds__(64 * WPG) push_fast_kernel(PushArgs a)
         // Step-ahead loads: the levels of step n+1 on the nodes any lane can
         // reach from this step's cells (all within rad of cref).
         const bool pf_next = st + 1 < S_run && rad >= 0 &&
-                             __all(!live || (cell >= cref - rad && cell <= cref + rad));
+                             (lmask & ~(wballot(cell >= cref - rad) & wballot(cell <= cref + rad))) == 0;
         const int nlo = cref - rad - margin - 1;
         if (pf_next) {
-            Levels<P> ln;
-#pragma unroll
-            for (int j = 0; j <= P; ++j) ln.off[j] = lvo[j + 1];
 #pragma unroll
             for (int h = 0; h < NPF; ++h) {
                 // value e = lane + 64 h: row e / 16 (level e / 32, field
                 // (e / 16) & 1), node nlo + e % 16
                 if (lane + 64 * h < ROWS * PF_NW) {
                     const int node = min(max(nlo + pf_q, 0), ncells - 1);
-                    const int32_t off = (lane & 32) ? ln.off[2 * h + 1] : ln.off[2 * h];
+                    const int32_t o_even = lvo[2 * h + 1], o_odd = lvo[2 * h + 2];
+                    const int32_t off = pf_hi ? o_odd : o_even;
                     pf[h] = pf_src[off + node];
                 }
             }
@@ -240,7 +244,8 @@ __global__ void __launch_bounds__(64 * WPG) push_fast_kernel(PushArgs a)
 
         // Does the window loaded during the previous step cover every lane?
         const bool use_win =
-            win && __all(!live || (cell - margin >= wlo && cell + margin + 1 < wlo + PF_NW));
+            win && (lmask & ~(wballot(cell - margin >= wlo) &
+                             wballot(cell + margin + 1 < wlo + PF_NW))) == 0;
 
         // decision: B at (x_n, s = 1/2), 1/gamma of the stored momentum
         int k = 0;
@@ -259,7 +264,7 @@ __global__ void __launch_bounds__(64 * WPG) push_fast_kernel(PushArgs a)
             Bd = tent_fma(x - fl, b0, b1);
             psi0 = fabs(c0 * Bd) * ig;
         }
-        if (__any(live && psi0 > psi_max)) {      // some lane sub-cycles
+        if (lmask & wballot(psi0 > psi_max)) {   // some lane sub-cycles
             if (live) {
                 double lim = psi_max;
                 while (psi0 > lim && k < kmax) {
@@ -268,15 +273,17 @@ __global__ void __launch_bounds__(64 * WPG) push_fast_kernel(PushArgs a)
                 }
                 clamped = psi0 > lim;
             }
-            cnt.clamps += __popcll(__ballot(clamped));
+            cnt.clamps += __popcll(wballot(clamped));
         }
-        if (tracing && live) ktrace_put(a, kt_u, n, int8_t(k));
+        if (tracing) {
+            if (live) ktrace_put(a, kt_u, n, int8_t(k));
+        }
         const bool heavy = live && k > 0;
 
         // A sub-cycled step outside the step-ahead window stages its own.
         bool lds = use_win;
         int base = wlo;
-        if (!use_win && __any(heavy)) {
+        if (!use_win && wany(heavy)) {
             const int lo = max(__builtin_amdgcn_readfirstlane(
                                    wave_min(heavy ? cell - margin : INT_MAX)), 0);
             const int hi = min(__builtin_amdgcn_readfirstlane(
@@ -365,7 +372,7 @@ __global__ void __launch_bounds__(64 * WPG) push_fast_kernel(PushArgs a)
             }
         }
         cnt.steps_done(done, k);
-        cnt.lost += __popcll(__ballot(live && !done));
+        cnt.lost += __popcll(wballot(live & !done));
 
         // hand the step-ahead window to LDS for the next step
         if (pf_next) {
