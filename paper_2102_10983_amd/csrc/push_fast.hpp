@@ -181,9 +181,15 @@ __global__ void __launch_bounds__(64 * WPG) push_fast_kernel(PushArgs a)
     }
     bool moved = false;
     const bool tracing = a.ktrace != nullptr;
+    // launch steps whose k is recorded: [kt_lo, kt_hi)
+    int kt_lo = 0, kt_hi = 0;
+    if (tracing) {
+        const int64_t lo = a.kt_n0 - n0, hi = lo + a.kt_steps;
+        kt_lo = int(lo < 0 ? 0 : (lo > S_run ? S_run : lo));
+        kt_hi = int(hi < 0 ? 0 : (hi > S_run ? S_run : hi));
+    }
     bool win = false;        // LDS holds this step's levels on nodes [wlo, wlo + PF_NW)
     int wlo = 0;
-    double pf[NPF];
     // this lane's share of the window: field (lane bit 4), level pair (bit
     // 5), node (bits 0..3); where it goes in LDS
     const gdptr pf_src = (lane & 16) ? ringB : ringE;
@@ -211,8 +217,11 @@ __global__ void __launch_bounds__(64 * WPG) push_fast_kernel(PushArgs a)
             cnt.lost += __popcll(amask & ~lmask);
             if ((status == PIC_PARTICLE_LIVE) & !live) status = PIC_PARTICLE_LOST;
         }
-        if (tracing) {
-            if (!live) ktrace_put(a, kt_u, n, -1);
+        // k trace: the row of this step, if it is recorded (wave-uniform)
+        const bool trace_now = st >= kt_lo && st < kt_hi;
+        const int64_t kt_row = n - a.kt_n0;
+        if (trace_now) {
+            if (!live && kt_u >= 0) a.ktrace[kt_row * a.kt_count + kt_u] = -1;
         }
         if (!lmask) {
             for (int s2 = st + 1; s2 < S_run; ++s2) ktrace_put(a, kt_u, n0 + s2, -1);
@@ -228,6 +237,7 @@ __global__ void __launch_bounds__(64 * WPG) push_fast_kernel(PushArgs a)
         const bool pf_next = st + 1 < S_run && rad >= 0 &&
                              (lmask & ~(wballot(cell >= cref - rad) & wballot(cell <= cref + rad))) == 0;
         const int nlo = cref - rad - margin - 1;
+        double pf[NPF];
         if (pf_next) {
 #pragma unroll
             for (int h = 0; h < NPF; ++h) {
@@ -275,8 +285,8 @@ __global__ void __launch_bounds__(64 * WPG) push_fast_kernel(PushArgs a)
             }
             cnt.clamps += __popcll(wballot(clamped));
         }
-        if (tracing) {
-            if (live) ktrace_put(a, kt_u, n, int8_t(k));
+        if (trace_now) {
+            if (live && kt_u >= 0) a.ktrace[kt_row * a.kt_count + kt_u] = int8_t(k);
         }
         const bool heavy = live && k > 0;
 
