@@ -164,6 +164,30 @@ pic_status pic_fields_load_lattice(pic_ctx *ctx, int64_t n_first,
                                    int64_t cE, int64_t aB, int64_t bB,
                                    int64_t cB);
 
+/* Standard PIC fields (Sec. III, Eqs. (Ey) and (Bz)): compute levels
+ * n_first .. n_first + count - 1 with the 1D Yee scheme from level
+ * n_first - 1, which must be in the ring (PIC_E_LEVEL otherwise), and
+ * store each in its ring slot.  nu = dt / dx.  Boundaries (not given by
+ * the paper; chosen here): the laser enters at node 0, where B_z of level
+ * m is the incident wave table[(aB m + cB) mod M] (a hard source; table is
+ * a device array of M doubles, as for pic_fields_load_lattice); the last E
+ * node obeys the first-order Mur one-way condition with kappa =
+ * (dt - dx) / (dt + dx).  IEEE arithmetic in the order of the equations:
+ * the levels are bit-identical to a CPU loop.  count <= ring_depth - 1.
+ * Asynchronous on the context's stream.  A typical run loads the levels
+ * n0 - order .. n0 with pic_fields_load_lattice (or pic_fields_load) and
+ * lets the solver make every later level. */
+pic_status pic_fields_yee(pic_ctx *ctx, int64_t n_first, int32_t count,
+                          const double *table, int64_t M, int64_t aB,
+                          int64_t cB);
+
+/* Copy ring level n of a run out (Ey, Bz: ncells doubles each, either may
+ * be NULL; host or device memory; PIC_E_LEVEL if the ring does not hold
+ * level n, and for runs in device-driven mode, whose ring is filled on the
+ * device).  With PIC_MEM_HOST the call synchronises the stream. */
+pic_status pic_fields_read(pic_ctx *ctx, int64_t n, pic_mem mem, double *Ey,
+                           double *Bz);
+
 /* Advance every live particle from x at n dt to (n + S) dt: S steps of
  * Algorithm 1 (Sec. IV) with order-p interpolation (Sec. VI).  Requires
  * levels n - order .. n + S - 1 in the ring (PIC_E_LEVEL otherwise, and
@@ -211,6 +235,14 @@ pic_status pic_fields_load_lattice_r(pic_ctx *ctx, int32_t run,
                                      const double *table, int64_t M,
                                      int64_t aE, int64_t bE, int64_t cE,
                                      int64_t aB, int64_t bB, int64_t cB);
+
+/* Yee levels and level read-out for one run (see pic_fields_yee,
+ * pic_fields_read). */
+pic_status pic_fields_yee_r(pic_ctx *ctx, int32_t run, int64_t n_first,
+                            int32_t count, const double *table, int64_t M,
+                            int64_t aB, int64_t cB);
+pic_status pic_fields_read_r(pic_ctx *ctx, int32_t run, int64_t n, pic_mem mem,
+                             double *Ey, double *Bz);
 
 /* Device-driven mode.  Attach a phase table (device array of M doubles,
  * coefficients as in pic_fields_load_lattice, kept valid by the caller)

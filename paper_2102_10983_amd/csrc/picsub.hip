@@ -38,6 +38,7 @@
 #include "setup.hpp"
 #include "mlp.hpp"
 #include "push_fast.hpp"
+#include "fields_yee.hpp"
 
 using namespace picsub;
 
@@ -660,6 +661,66 @@ pic_status pic_fields_load_lattice(pic_ctx *ctx, int64_t n_first, int32_t count,
                                    int64_t bB, int64_t cB)
 {
     return pic_fields_load_lattice_r(ctx, 0, n_first, count, table, M, aE, bE, cE, aB, bB, cB);
+}
+
+pic_status pic_fields_yee_r(pic_ctx *ctx, int32_t run, int64_t n_first, int32_t count,
+                           const double *table, int64_t M, int64_t aB, int64_t cB)
+{
+    CTX_CHECK(ctx);
+    if (run < 0 || run >= ctx->nruns) return fail(ctx, PIC_E_ARG, "bad run %d", run);
+    if (!table || M <= 0) return fail(ctx, PIC_E_ARG, "bad table");
+    RunHost &R = ctx->runs[size_t(run)];
+    const int D = R.prm.ring_depth;
+    const int32_t N = R.prm.ncells;
+    if (count < 0 || count > D - 1) return fail(ctx, PIC_E_ARG, "count must be in [0, ring_depth - 1]");
+    if (N < 2) return fail(ctx, PIC_E_ARG, "the Yee solver needs two or more cells");
+    if (count == 0) return PIC_OK;
+    if (R.tags[size_t(mod_floor(n_first - 1, D))] != n_first - 1)
+        return fail(ctx, PIC_E_LEVEL, "level %lld (the solver's start) is not in the ring",
+                    (long long)(n_first - 1));
+    const double dx = R.prm.dx, dt = R.prm.dt;
+    const double nu = dt / dx, kappa = (dt - dx) / (dt + dx);
+    constexpr int WT = 64 * YEE_R - 2 * (YEE_T + 2);
+    const unsigned tiles = unsigned((N + WT - 1) / WT);
+    const int per = std::min(YEE_T, D - 1);
+    for (int32_t c = 0; c < count; c += per) {
+        const int cnt = std::min(per, count - c);
+        yee_kernel<YEE_R, YEE_T><<<tiles, 64, 0, ctx->stream>>>(R.ringE, R.ringB, D, N,
+                                                                 n_first + c, cnt, nu, kappa,
+                                                                 table, M, aB, cB);
+        LAUNCH_CHECK(ctx);
+    }
+    for (int32_t c = 0; c < count; ++c) R.tags[size_t(mod_floor(n_first + c, D))] = n_first + c;
+    return PIC_OK;
+}
+
+pic_status pic_fields_yee(pic_ctx *ctx, int64_t n_first, int32_t count, const double *table,
+                         int64_t M, int64_t aB, int64_t cB)
+{
+    return pic_fields_yee_r(ctx, 0, n_first, count, table, M, aB, cB);
+}
+
+pic_status pic_fields_read_r(pic_ctx *ctx, int32_t run, int64_t n, pic_mem mem, double *Ey,
+                             double *Bz)
+{
+    CTX_CHECK(ctx);
+    if (run < 0 || run >= ctx->nruns) return fail(ctx, PIC_E_ARG, "bad run %d", run);
+    if (mem != PIC_MEM_HOST && mem != PIC_MEM_DEVICE) return fail(ctx, PIC_E_ARG, "bad pic_mem");
+    RunHost &R = ctx->runs[size_t(run)];
+    const int64_t slot = mod_floor(n, R.prm.ring_depth);
+    if (R.driven || R.tags[size_t(slot)] != n)
+        return fail(ctx, PIC_E_LEVEL, "level %lld is not in the ring", (long long)n);
+    const size_t bytes = size_t(R.prm.ncells) * sizeof(double);
+    const hipMemcpyKind kind = mem == PIC_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+    if (Ey) HIP_TRY(ctx, hipMemcpyAsync(Ey, R.ringE + slot * R.prm.ncells, bytes, kind, ctx->stream));
+    if (Bz) HIP_TRY(ctx, hipMemcpyAsync(Bz, R.ringB + slot * R.prm.ncells, bytes, kind, ctx->stream));
+    if (mem == PIC_MEM_HOST) HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    return PIC_OK;
+}
+
+pic_status pic_fields_read(pic_ctx *ctx, int64_t n, pic_mem mem, double *Ey, double *Bz)
+{
+    return pic_fields_read_r(ctx, 0, n, mem, Ey, Bz);
 }
 
 pic_status pic_source_set(pic_ctx *ctx, int32_t run, int64_t n_start, int64_t n_stop,

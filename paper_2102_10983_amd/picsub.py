@@ -32,7 +32,8 @@ EXPORTS = ("pic_create", "pic_destroy", "pic_last_error", "pic_particles_set",
            "pic_run_counters", "pic_tune_set", "pic_tune_get", "pic_autotune",
            "pic_group_count", "pic_order_set", "pic_features", "pic_mlp_forward",
            "pic_mlp_grad", "pic_mlp_adam", "pic_prebin", "pic_state_export",
-           "pic_state_import")
+           "pic_state_import", "pic_fields_yee", "pic_fields_yee_r", "pic_fields_read",
+           "pic_fields_read_r")
 
 MLP_FEATURES = 8
 MLP_HIDDEN = 64
@@ -125,6 +126,10 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "pic_prebin": ([vp, vp, i32, C.c_float, i32], C.c_int),
         "pic_state_export": ([vp, vp, C.POINTER(C.c_size_t)], C.c_int),
         "pic_state_import": ([vp, vp, C.c_size_t, vp], C.c_int),
+        "pic_fields_yee": ([vp, i64, i32, vp, i64, i64, i64], C.c_int),
+        "pic_fields_yee_r": ([vp, i32, i64, i32, vp, i64, i64, i64], C.c_int),
+        "pic_fields_read": ([vp, i64, C.c_int, vp, vp], C.c_int),
+        "pic_fields_read_r": ([vp, i32, i64, C.c_int, vp, vp], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -274,6 +279,25 @@ class Pusher:
         tp = _dev_ptr(table, torch.float64)
         self._check(self._lib.pic_fields_load_lattice_r(self._ctx, run, n_first, count, tp, M,
                                                         *[int(c) for c in coeffs]))
+
+    def fields_yee(self, n_first: int, count: int, table, M: int, aB: int, cB: int, run: int = 0):
+        """Levels n_first .. n_first + count - 1 of a run by the Yee scheme
+        from level n_first - 1; the laser source is table[(aB m + cB) mod M]."""
+        torch = _torch()
+        tp = _dev_ptr(table, torch.float64)
+        if table.numel() < M:
+            raise ValueError("table shorter than M")
+        self._check(self._lib.pic_fields_yee_r(self._ctx, run, n_first, count, tp, M,
+                                               int(aB), int(cB)))
+
+    def fields_read(self, n: int, run: int = 0):
+        """(Ey, Bz) of ring level n as host arrays."""
+        nc = self.params[run].ncells
+        E = np.empty(nc)
+        B = np.empty(nc)
+        self._check(self._lib.pic_fields_read_r(self._ctx, run, n, MEM_HOST, E.ctypes.data,
+                                                B.ctypes.data))
+        return E, B
 
     def push(self, n: int, S: int = 1):
         self._check(self._lib.pic_push_subcycled(self._ctx, n, S))

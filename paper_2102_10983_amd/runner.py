@@ -10,13 +10,21 @@ from . import workloads as W
 
 
 class DeviceRun:
-    """A Pusher bound to one workload, with its phase table on the device."""
+    """A Pusher bound to one workload, with its phase table on the device.
+
+    fields="lattice": every level sampled from the phase table (the
+    prescribed wave, "perfectly propagating PIC").  fields="yee": levels
+    -order .. 0 sampled, every later level made by the Yee solver with the
+    wave entering at node 0 ("standard PIC")."""
 
     def __init__(self, wl: W.Workload, *, S: int = 1, order: int | None = None,
                  psi_max: float | None = None, precision: str = "fp64", binning: str = "ballot",
-                 k_max: int = 8, ring_extra: int = 0, stream=None):
+                 k_max: int = 8, ring_extra: int = 0, stream=None, fields: str = "lattice"):
         import torch
+        if fields not in ("lattice", "yee"):
+            raise ValueError("fields must be 'lattice' or 'yee'")
         self.torch = torch
+        self.fields = fields
         self.wl = wl
         self.order = wl.order if order is None else order
         self.S = int(S)
@@ -37,7 +45,8 @@ class DeviceRun:
     def reset(self, k_old=None):
         """Load the initial state (device to device) and the first levels."""
         self.pusher.particles_set(self.x0, *self.p0, k_old)
-        self.pusher.fields_load_lattice(-self.order, self.order, self.table, self.M, self.coeffs)
+        first = self.order + (1 if self.fields == "yee" else 0)
+        self.pusher.fields_load_lattice(-self.order, first, self.table, self.M, self.coeffs)
         self.n = 0
 
     def advance(self, steps: int, S: int | None = None):
@@ -46,9 +55,19 @@ class DeviceRun:
         end = self.n + steps
         while self.n < end:
             s = min(S, end - self.n)
-            self.pusher.fields_load_lattice(self.n, s, self.table, self.M, self.coeffs)
+            self.fill(self.n, s)
             self.pusher.push(self.n, s)
             self.n += s
+
+    def fill(self, n: int, s: int):
+        """Put levels n .. n + s - 1 into the ring."""
+        if self.fields == "lattice":
+            self.pusher.fields_load_lattice(n, s, self.table, self.M, self.coeffs)
+        else:
+            lo = max(n, 1)              # level 0 was sampled by reset()
+            if n + s > lo:
+                self.pusher.fields_yee(lo, n + s - lo, self.table, self.M, self.coeffs[3],
+                                       self.coeffs[5])
 
     def diag(self):
         return self.pusher.diag()

@@ -29,13 +29,35 @@ def oracle_params(wl: W.Workload, order=None, psi_max=None, k_max=8):
                          wl.psi_max if psi_max is None else psi_max, wl.x_origin, k_max=k_max)
 
 
+def oracle_yee_fields(wl: W.Workload, steps: int):
+    """Standard PIC levels for the oracle: levels -order .. 0 sampled from
+    the phase table, levels 1 .. steps - 1 from the FP64 Yee reference with
+    the wave entering at node 0."""
+    from oracle import yee_ref as Y
+    table, M, shift = wl.table()
+    aE, bE, cE, aB, bB, cB = (int(c) for c in W.shifted_coeffs(wl.lat, shift))
+    p = wl.order
+    i = np.arange(wl.ncells, dtype=np.int64)
+    E = np.empty((steps + p, wl.ncells))
+    B = np.empty((steps + p, wl.ncells))
+    for j, m in enumerate(range(-p, 1)):
+        E[j] = table[(aE * m + bE * i + cE) % M]
+        B[j] = table[(aB * m + bB * i + cB) % M]
+    if steps > 1:
+        El, Bl = Y.advance_lattice(E[p], B[p], wl.dx, wl.dt, 1, steps - 1, table, aB, cB)
+        E[p + 1:] = El
+        B[p + 1:] = Bl
+    return O.FieldSource(E=E, B=B, lev0=-p)
+
+
 def oracle_run(wl, steps, idx=None, order=None, psi_max=None, trace=False, forced_k=None,
-               k_old=None, threads=0):
+               k_old=None, threads=0, fields=None):
     idx = np.arange(wl.num) if idx is None else np.asarray(idx)
     st = O.State(wl.x0[idx], wl.p0[0][idx], wl.p0[1][idx], wl.p0[2][idx],
                  k_old=None if k_old is None else np.asarray(k_old)[idx])
     cnt = O.Counters()
-    kt, pt = O.push(oracle_params(wl, order, psi_max), oracle_fields(wl), st, 0, steps,
+    fs = oracle_fields(wl) if fields is None else fields
+    kt, pt = O.push(oracle_params(wl, order, psi_max), fs, st, 0, steps,
                     trace=trace, psi_trace=trace, forced_k=forced_k, counters=cnt,
                     threads=threads)
     return st, cnt, kt, pt
@@ -51,7 +73,7 @@ def errors(gx, gpx, gpy, gpz, st: O.State, x0):
 
 
 def compare(wl, steps, gdiag, idx, tol, g_ktrace=None, order=None, psi_max=None,
-            flip_rel=1e-9):
+            flip_rel=1e-9, fields=None):
     """Compare device results (caller order, full arrays) on particles idx.
 
     flip_rel bounds how far from a threshold psi_max 4^k the first differing
@@ -60,7 +82,7 @@ def compare(wl, steps, gdiag, idx, tol, g_ktrace=None, order=None, psi_max=None,
     Returns a dict of statistics; raises AssertionError on a violation."""
     idx = np.asarray(idx)
     st, cnt, kt, pt = oracle_run(wl, steps, idx, order=order, psi_max=psi_max,
-                                 trace=g_ktrace is not None)
+                                 trace=g_ktrace is not None, fields=fields)
     gx, gpx, gpy, gpz = (gdiag[k][idx] for k in ("x", "px", "py", "pz"))
     out = {"n": len(idx), "flips": 0, "bitwise": 0}
     same = np.ones(len(idx), dtype=bool)
@@ -78,7 +100,8 @@ def compare(wl, steps, gdiag, idx, tol, g_ktrace=None, order=None, psi_max=None,
                 assert r > 0 and abs(r / 4.0 ** (kk - 1) - 1) < flip_rel, (c, s0, r, gk[s0, c],
                                                                            kt[s0, c])
             fst, _, _, _ = oracle_run(wl, steps, idx[~same], order=order, psi_max=psi_max,
-                                      forced_k=np.ascontiguousarray(gk[:, ~same]))
+                                      forced_k=np.ascontiguousarray(gk[:, ~same]),
+                                      fields=fields)
             st.x[~same], st.px[~same], st.py[~same], st.pz[~same] = fst.x, fst.px, fst.py, fst.pz
             st.status[~same] = fst.status
     e_p, e_x = errors(gx, gpx, gpy, gpz, st, wl.x0[idx])
