@@ -105,9 +105,10 @@ class Pass:
     host-driven launches of S steps) or on a batch of runs (device-driven
     windows of S steps, each run stopping at its own step count)."""
 
-    def __init__(self, wl, S, precision, binning, predictor=None):
+    def __init__(self, wl, S, precision, binning, predictor=None, fields="lattice"):
         from paper_2102_10983_amd import runner
         self.wl = wl
+        self.fill_events = []
         self.S = S
         self.binning = binning
         self.predictor = predictor
@@ -119,7 +120,8 @@ class Pass:
             self.pusher = self.run.pusher
             self.a0 = [w.a0 for w in wl]
         else:
-            self.run = runner.DeviceRun(wl, S=S, precision=precision, binning=kernel_binning)
+            self.run = runner.DeviceRun(wl, S=S, precision=precision, binning=kernel_binning,
+                                        fields=fields)
             self.pusher = self.run.pusher
             self.a0 = wl.a0
 
@@ -145,7 +147,15 @@ class Pass:
             return
         while run.n < wl.steps:
             s = min(self.S, wl.steps - run.n)
-            run.pusher.fields_load_lattice(run.n, s, run.table, run.M, run.coeffs)
+            if events is not None:
+                f0 = torch.cuda.Event(enable_timing=True)
+                f1 = torch.cuda.Event(enable_timing=True)
+                f0.record(stream)
+                run.fill(run.n, s)
+                f1.record(stream)
+                self.fill_events.append((f0, f1))
+            else:
+                run.fill(run.n, s)
             if events is not None:
                 e0 = torch.cuda.Event(enable_timing=True)
                 e1 = torch.cuda.Event(enable_timing=True)
@@ -258,18 +268,29 @@ def main():
 
     compare = []
     if not args.no_compare:
-        for label, prec, binning in (("plain binning, same precision", args.precision, "none"),
-                                     ("plain FP64 push (IEEE div/sqrt)", "fp64", "none")):
-            if prec == args.precision and binning == args.binning:
+        legs = [("plain binning, same precision", args.precision, "none", "lattice"),
+                ("plain FP64 push (IEEE div/sqrt)", "fp64", "none", "lattice")]
+        if args.workload == "large":
+            legs.append(("standard PIC: levels from the Yee solver, same precision and binning",
+                         args.precision, args.binning, "yee"))
+        for label, prec, binning, fields in legs:
+            if prec == args.precision and binning == args.binning and fields == "lattice":
                 continue
-            p = Pass(wl, S, prec, binning)
-            t = p.time(args.steps, args.warmup, stream)
+            p = Pass(wl, S, prec, binning, model if binning == "learned" else None, fields)
+            p.pb_width = args.pb_width
+            ev = [] if fields == "yee" else None
+            t = p.time(args.steps, args.warmup, stream, ev)
             c = p.pusher.counters()
+            leg = {"label": label, "precision": prec, "binning": binning, "fields": fields,
+                   "ms_per_step": t / args.steps * 1e3,
+                   "value": c["sub_steps"] * args.steps / t,
+                   "same_sub_steps": c["sub_steps"] == sub_per_step}
+            if ev is not None:
+                leg["push_ms"] = sum(a.elapsed_time(b) for a, b in ev) / args.steps
+                leg["field_solve_ms"] = sum(a.elapsed_time(b) for a, b in p.fill_events) / args.steps
+                leg["sub_steps_per_pass"] = c["sub_steps"]
             p.close()
-            compare.append({"label": label, "precision": prec, "binning": binning,
-                            "ms_per_step": t / args.steps * 1e3,
-                            "value": c["sub_steps"] * args.steps / t,
-                            "same_sub_steps": c["sub_steps"] == sub_per_step})
+            compare.append(leg)
 
     res = {
         "metric": "sub-step particle pushes/sec at rel err<=1e-5 vs FP64 oracle; "

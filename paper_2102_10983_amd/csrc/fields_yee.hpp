@@ -27,8 +27,8 @@
 
 namespace picsub {
 
-constexpr int YEE_R = 8;     // nodes per lane
-constexpr int YEE_T = 64;    // levels per launch (at most)
+constexpr int YEE_R = 2;     // nodes per lane
+constexpr int YEE_T = 40;    // levels per launch (at most)
 
 template <int R, int T>
 __global__ void __launch_bounds__(64) yee_kernel(double *__restrict__ ringE,
@@ -52,8 +52,12 @@ __global__ void __launch_bounds__(64) yee_kernel(double *__restrict__ ringE,
         e[r] = in ? ringE[prev + i] : 0.0;
         b[r] = in ? ringB[prev + i] : 0.0;
     }
+    // ring slot and source-table index of the level being made, moved on
+    // by one level per pass (no division in the loop)
+    int32_t slot = int32_t(mod_floor(n_first, D));
+    int64_t q = mod_floor(aB * n_first + cB, M);
+    const int64_t dq = mod_floor(aB, M);
     for (int c = 0; c < count; ++c) {
-        const int64_t m = n_first + c;
         // E: B of the node to the right (the next lane's first node)
         const double bnext = __shfl_down(b[0], 1);
         double en[R];
@@ -84,22 +88,25 @@ __global__ void __launch_bounds__(64) yee_kernel(double *__restrict__ ringE,
         }
         // left end: the incident wave at node 0
         if (base <= 0 && 0 < base + R) {
-            const double src = table[mod_floor(aB * m + cB, M)];
+            const double src = table[q];
 #pragma unroll
             for (int r = 0; r < R; ++r)
                 if (base + r == 0) bn[r] = src;
         }
-        const int64_t slot = mod_floor(m, D) * ncells;
+        const int64_t off = int64_t(slot) * ncells;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int i = base + r;
             if (i >= t0 && i < t0 + WT && i < ncells) {
-                ringE[slot + i] = en[r];
-                ringB[slot + i] = bn[r];
+                ringE[off + i] = en[r];
+                ringB[off + i] = bn[r];
             }
             e[r] = en[r];
             b[r] = bn[r];
         }
+        slot = slot + 1 == D ? 0 : slot + 1;
+        q += dq;
+        if (q >= M) q -= M;
     }
 }
 
