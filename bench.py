@@ -195,6 +195,9 @@ def main():
     ap.add_argument("--S", type=int, default=0,
                     help="steps of dt per push launch (0: the whole run in one launch)")
     ap.add_argument("--precision", default="fp64fast", choices=("fp64", "fp32c", "fp64fast"))
+    ap.add_argument("--fields", default="lattice", choices=("lattice", "yee"),
+                    help="large/stress: field levels sampled from the prescribed wave "
+                         "(perfectly propagating PIC) or made by the Yee solver (standard PIC)")
     ap.add_argument("--binning", default="learned", choices=("none", "ballot", "learned"))
     ap.add_argument("--num", type=int, default=0,
                     help="electrons (large: 2^20, stress: 2^24; batch: scale factor x 1e6)")
@@ -248,7 +251,11 @@ def main():
     model = PR.Predictor.load() if args.binning == "learned" else None
     stream = torch.cuda.current_stream()
 
-    main_pass = Pass(wl, S, args.precision, args.binning, model)
+    if args.workload == "batch" and args.fields != "lattice":
+        print("the batch workload samples its fields on the device (--fields lattice)",
+              file=sys.stderr)
+        sys.exit(2)
+    main_pass = Pass(wl, S, args.precision, args.binning, model, args.fields)
     main_pass.pb_width = args.pb_width
     events = []
     elapsed = main_pass.time(args.steps, args.warmup, stream, events)
@@ -264,17 +271,22 @@ def main():
     flops_step = algorithmic_flops(counters, order)
     achieved = flops_step * args.steps / (kernel_ms / 1e3) / 1e12
     key = "ballot" if args.binning == "ballot" else args.precision
-    traffic = measured_traffic(key, launches_per_step) if args.workload == "large" else None
+    traffic = (measured_traffic(key, launches_per_step)
+               if args.workload == "large" and args.fields == "lattice" else None)
+    solve_ms = (sum(a.elapsed_time(b) for a, b in main_pass.fill_events) / args.steps
+                if args.fields == "yee" else None)
 
     compare = []
     if not args.no_compare:
-        legs = [("plain binning, same precision", args.precision, "none", "lattice"),
-                ("plain FP64 push (IEEE div/sqrt)", "fp64", "none", "lattice")]
+        legs = [("plain binning, same precision", args.precision, "none", args.fields),
+                ("plain FP64 push (IEEE div/sqrt)", "fp64", "none", args.fields)]
         if args.workload == "large":
-            legs.append(("standard PIC: levels from the Yee solver, same precision and binning",
-                         args.precision, args.binning, "yee"))
+            other = "yee" if args.fields == "lattice" else "lattice"
+            legs.append(({"yee": "standard PIC: levels from the Yee solver",
+                          "lattice": "perfectly propagating PIC: levels sampled from the wave"}[other]
+                         + ", same precision and binning", args.precision, args.binning, other))
         for label, prec, binning, fields in legs:
-            if prec == args.precision and binning == args.binning and fields == "lattice":
+            if prec == args.precision and binning == args.binning and fields == args.fields:
                 continue
             p = Pass(wl, S, prec, binning, model if binning == "learned" else None, fields)
             p.pb_width = args.pb_width
@@ -307,10 +319,11 @@ def main():
         "dtype": {"fp64": "f64", "fp64fast": "f64", "fp32c": "f32+f64"}[args.precision],
         "data": "synthetic",
         "config": {"workload": wdesc,
-                   "precision": args.precision, "binning": args.binning,
+                   "precision": args.precision, "binning": args.binning, "fields": args.fields,
                    "steps_per_launch": S, "sub_steps_per_pass": sub_per_step,
                    "mean_sub_steps_per_particle_step": sub_per_step / counters["steps"],
-                   "n_star": counters["n_star"], "steps_by_k": counters["steps_by_k"][:9]},
+                   "n_star": counters["n_star"], "steps_by_k": counters["steps_by_k"][:9],
+                   **({"field_solve_ms": solve_ms} if solve_ms is not None else {})},
         "compare": compare,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
@@ -318,7 +331,7 @@ def main():
                      "avg_launch_ms": kernel_ms / launches,
                      "flops_per_launch": flops_step * args.steps / launches},
     }
-    if not args.no_cpu and args.workload == "large":
+    if not args.no_cpu and args.workload == "large" and args.fields == "lattice":
         threads = len(os.sched_getaffinity(0))
         res["cpu_baseline"] = cpu_baseline(wl, args.cpu_every, threads)
     print(json.dumps(res))
