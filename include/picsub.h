@@ -274,6 +274,31 @@ pic_status pic_graph_release(pic_ctx *ctx);
 /* Counters of one run (synchronises the stream). */
 pic_status pic_run_counters(pic_ctx *ctx, int32_t run, pic_counters *cnt);
 
+/* ------------------------------------------------------------------
+ * Dephasing diagnostic (Sec. V, Eq. (R error)).  R = gamma - p_x of the
+ * stored momentum is 1 for an electron that starts at rest in a plane
+ * wave in vacuum and stays at its initial value R0 for any start (App. A),
+ * so max |R - R0| / R0 over a trajectory measures the integrator's error
+ * (the paper's epsilon_dephasing when R0 = 1).
+ * ------------------------------------------------------------------ */
+
+/* on = 1: (re)start: R0 := R of every particle now, running maximum := 0;
+ * from then on every push kernel updates the maximum of |R - R0| / R0
+ * after each completed step of a live particle (one square root and one
+ * division per particle-step, IEEE, the same in every precision mode).
+ * on = 0: stop updating (the values are kept).  Loading particles restarts
+ * it while on; re-binning (pic_prebin) carries it with the particles; the
+ * autotuner's trials do not touch it; a captured graph keeps the setting
+ * it was captured with; checkpoints do not include it. */
+pic_status pic_dephasing_track(pic_ctx *ctx, int32_t on);
+
+/* R0 and the running maximum of every particle in caller order (np
+ * doubles each, either may be NULL; host or device memory).
+ * PIC_E_STATE if the diagnostic was never switched on.  With
+ * PIC_MEM_HOST the call synchronises the stream. */
+pic_status pic_dephasing_read(pic_ctx *ctx, pic_mem mem, double *R0,
+                              double *rmax);
+
 /* ------------------------------------------------------------------ */
 /* Launch shape.  None of these knobs changes a result: every kernel    */
 /* gives each particle the same arithmetic whichever lane runs it.      */

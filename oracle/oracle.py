@@ -190,5 +190,35 @@ def push(prm: Params, fs: FieldSource, st: State, n0: int, nsteps: int, *,
     return kt, pt
 
 
+def dephasing_R(px, py, pz):
+    """R = gamma - p_x (Sec. V), gamma = sqrt(1 + ((p_x^2 + p_y^2) + p_z^2))."""
+    px = np.asarray(px, dtype=np.float64)
+    py = np.asarray(py, dtype=np.float64)
+    pz = np.asarray(pz, dtype=np.float64)
+    return np.sqrt(1.0 + ((px * px + py * py) + pz * pz)) - px
+
+
+def push_dephasing(prm: Params, fs: FieldSource, st: State, n0: int, nsteps: int, *,
+                   forced_k=None, counters: Counters | None = None, threads: int = 0):
+    """push() one step at a time, recording after every completed step of a
+    live particle the dephasing error |R - R0| / R0 of Eq. (R error), R0
+    being R of the state passed in; returns (R0, the running maximum, the k
+    trace [nsteps, num])."""
+    R0 = dephasing_R(st.px, st.py, st.pz)
+    rmax = np.zeros(st.num)
+    kt = np.empty((nsteps, st.num), dtype=np.int8)
+    cnt = counters if counters is not None else Counters()
+    for c in range(nsteps):
+        live_before = st.status == 0
+        fk = None if forced_k is None else np.ascontiguousarray(forced_k[c:c + 1])
+        k1, _ = push(prm, fs, st, n0 + c, 1, forced_k=fk, trace=True, counters=cnt,
+                     threads=threads)
+        kt[c] = k1[0]
+        done = live_before & (st.status == 0)
+        d = np.abs(dephasing_R(st.px, st.py, st.pz) - R0) / R0
+        rmax = np.where(done & (d > rmax), d, rmax)
+    return R0, rmax, kt
+
+
 def max_threads() -> int:
     return int(lib().orc_max_threads())

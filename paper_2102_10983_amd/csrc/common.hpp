@@ -48,6 +48,8 @@ struct PushArgs {
     const int32_t *perm;              // slot -> caller index (-1: padding)
     const double *wtab;
     int8_t *ktrace;
+    const double *r0;                 // dephasing diagnostic (null: off): R = gamma - p_x at
+    double *rmax;                     //   the start, running max of |R - R0| / R0
     uint64_t *cnt;                    // [nruns][NSLOT][NCNT]
     int64_t kt_n0, kt_first, kt_count;
     int64_t n0;                       // NO_LEVEL: every run starts at its n_cur
@@ -295,6 +297,17 @@ __device__ __forceinline__ int run_steps(const PushArgs &a, const RunDesc &R, in
     if (a.n0 != NO_LEVEL) return a.S;                 // host-driven launch
     const int64_t left = R.n_stop - n0;
     return left <= 0 ? 0 : (left < a.S ? int(left) : a.S);
+}
+
+// Dephasing diagnostic (Sec. V, Eq. (R error)): after a completed step,
+// R = gamma - p_x of the stored momentum; keep the largest |R - R0| / R0.
+// IEEE square root and division, the order of a CPU loop.
+__device__ __forceinline__ void dephasing_update(double &rmax, double r0, double px, double py,
+                                                 double pz)
+{
+    const double g = sqrt(1.0 + ((px * px + py * py) + pz * pz));
+    const double d = fabs((g - px) - r0) / r0;
+    rmax = d > rmax ? d : rmax;
 }
 
 __device__ __forceinline__ void ktrace_put(const PushArgs &a, int64_t kt_u, int64_t n, int8_t v)

@@ -364,6 +364,21 @@ __global__ void permute_state_kernel(const int32_t *__restrict__ dest, int64_t s
     }
 }
 
+// Two per-slot FP64 arrays moved to the slots permute_state_kernel gives.
+__global__ void permute_pair_kernel(const int32_t *__restrict__ dest, int64_t slots,
+                                    const int32_t *__restrict__ perm,
+                                    const double *__restrict__ a, const double *__restrict__ b,
+                                    double *__restrict__ na, double *__restrict__ nb)
+{
+    for (int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; s < slots;
+         s += int64_t(gridDim.x) * blockDim.x) {
+        if (perm[s] < 0) continue;
+        const int32_t d = dest[s];
+        na[d] = a[s];
+        nb[d] = b[s];
+    }
+}
+
 // Predicted cost of each group: largest score of its lanes (LPT key).
 __global__ void group_cost_kernel(const float *__restrict__ score, const int32_t *__restrict__ perm,
                                   int32_t ngroups, float *__restrict__ gcost)

@@ -80,6 +80,9 @@ struct pic_ctx {
     int32_t ngroups = 0;
     double *wtab = nullptr;
     uint64_t *cnt = nullptr;
+    // dephasing diagnostic (allocated when first switched on)
+    double *r0 = nullptr, *rmax = nullptr;
+    bool deph = false;
     // k trace
     int8_t *ktrace = nullptr;
     int64_t kt_n0 = 0, kt_first = 0, kt_count = 0;
@@ -144,7 +147,8 @@ void free_all(pic_ctx *c)
     c->gexec = nullptr;
     c->graph = nullptr;
     void *ptrs[] = {c->x, c->px, c->py, c->pz, c->kold, c->status, c->perm, c->key,
-                    c->d_runs, c->group_run, c->group_order, c->group_prio, c->wtab, c->cnt};
+                    c->d_runs, c->group_run, c->group_order, c->group_prio, c->wtab, c->cnt,
+                    c->r0, c->rmax};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (RunHost &r : c->runs) {
@@ -159,6 +163,8 @@ void free_all(pic_ctx *c)
     c->group_prio = nullptr;
     c->d_runs = nullptr;
     c->cnt = nullptr;
+    c->r0 = c->rmax = nullptr;
+    c->deph = false;
 }
 
 pic_status check_params(pic_ctx *ctx, const pic_params *p, int64_t np, int r)
@@ -260,6 +266,8 @@ PushArgs push_args(pic_ctx *ctx, int64_t n0, int32_t S)
     a.perm = ctx->perm;
     a.wtab = ctx->wtab;
     a.ktrace = ctx->ktrace;
+    a.r0 = ctx->deph ? ctx->r0 : nullptr;
+    a.rmax = ctx->deph ? ctx->rmax : nullptr;
     a.cnt = ctx->cnt;
     a.kt_n0 = ctx->kt_n0;
     a.kt_first = ctx->kt_first;
@@ -271,35 +279,44 @@ PushArgs push_args(pic_ctx *ctx, int64_t n0, int32_t S)
     return a;
 }
 
-template <int P, int WPG>
+// DEPH: the dephasing diagnostic compiled in (only when it is switched on,
+// so the kernels without it keep their register budget)
+template <int P, int WPG, bool DEPH>
 void launch_wave(const PushArgs &a, int precision, hipStream_t s)
 {
     const dim3 grid(unsigned((a.ngroups + WPG - 1) / WPG)), block(64 * WPG);
     if (precision == PIC_FP64)
-        push_wave_kernel<P, WPG, Arith::IEEE64><<<grid, block, 0, s>>>(a);
+        push_wave_kernel<P, WPG, Arith::IEEE64, DEPH><<<grid, block, 0, s>>>(a);
     else if (precision == PIC_FP64_FAST)
-        push_fast_kernel<P, WPG><<<grid, block, 0, s>>>(a);
+        push_fast_kernel<P, WPG, DEPH><<<grid, block, 0, s>>>(a);
     else
-        push_wave_fp32c_kernel<P, WPG><<<grid, block, 0, s>>>(a);
+        push_wave_fp32c_kernel<P, WPG, DEPH><<<grid, block, 0, s>>>(a);
+}
+
+template <int P, bool DEPH>
+void launch_shape(const PushArgs &a, const pic_tune &t, int precision, int64_t slots, hipStream_t s)
+{
+    if (t.binning == PIC_BIN_BALLOT) {
+        const dim3 grid(unsigned(slots / t.tile));
+        switch (t.tile) {
+        case 128: push_tile_kernel<P, 128, DEPH><<<grid, dim3(128), 0, s>>>(a); break;
+        case 512: push_tile_kernel<P, 512, DEPH><<<grid, dim3(512), 0, s>>>(a); break;
+        default: push_tile_kernel<P, 256, DEPH><<<grid, dim3(256), 0, s>>>(a); break;
+        }
+        return;
+    }
+    switch (t.waves_per_group) {
+    case 2: launch_wave<P, 2, DEPH>(a, precision, s); break;
+    case 4: launch_wave<P, 4, DEPH>(a, precision, s); break;
+    default: launch_wave<P, 1, DEPH>(a, precision, s); break;
+    }
 }
 
 template <int P>
 void launch_order(const PushArgs &a, const pic_tune &t, int precision, int64_t slots, hipStream_t s)
 {
-    if (t.binning == PIC_BIN_BALLOT) {
-        const dim3 grid(unsigned(slots / t.tile));
-        switch (t.tile) {
-        case 128: push_tile_kernel<P, 128><<<grid, dim3(128), 0, s>>>(a); break;
-        case 512: push_tile_kernel<P, 512><<<grid, dim3(512), 0, s>>>(a); break;
-        default: push_tile_kernel<P, 256><<<grid, dim3(256), 0, s>>>(a); break;
-        }
-        return;
-    }
-    switch (t.waves_per_group) {
-    case 2: launch_wave<P, 2>(a, precision, s); break;
-    case 4: launch_wave<P, 4>(a, precision, s); break;
-    default: launch_wave<P, 1>(a, precision, s); break;
-    }
+    if (a.rmax) launch_shape<P, true>(a, t, precision, slots, s);
+    else launch_shape<P, false>(a, t, precision, slots, s);
 }
 
 pic_status launch_push(pic_ctx *ctx, int64_t n0, int32_t S, hipStream_t s)
@@ -594,6 +611,11 @@ pic_status load_particles(pic_ctx *ctx, pic_mem mem, const double *x, const doub
         e = hipMemcpyAsync(ctx->group_order, id.data(), id.size() * 4, hipMemcpyHostToDevice,
                            ctx->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    }
+    if (e == hipSuccess && ctx->deph) {          // new particles: the diagnostic restarts
+        dephasing_init_kernel<<<grid_for(ctx->slots, 256, 8192), 256, 0, ctx->stream>>>(
+            ctx->slots, ctx->px, ctx->py, ctx->pz, ctx->r0, ctx->rmax);
+        e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) result = fail(ctx, PIC_E_DEVICE, "particle load: %s", hipGetErrorString(e));
@@ -929,6 +951,63 @@ pic_status pic_diag(pic_ctx *ctx, pic_mem mem, double *gamma, double *px, double
     return PIC_OK;
 }
 
+pic_status pic_dephasing_track(pic_ctx *ctx, int32_t on)
+{
+    CTX_CHECK(ctx);
+    if (on != 0 && on != 1) return fail(ctx, PIC_E_ARG, "on must be 0 or 1");
+    if (!on) {
+        ctx->deph = false;
+        return PIC_OK;
+    }
+    const size_t n = size_t(ctx->slots);
+    pic_status st;
+    if (!ctx->r0) {
+        if ((st = dev_alloc(ctx, &ctx->r0, n))) return st;
+        if ((st = dev_alloc(ctx, &ctx->rmax, n))) {
+            (void)hipFree(ctx->r0);
+            ctx->r0 = nullptr;
+            return st;
+        }
+    }
+    dephasing_init_kernel<<<grid_for(ctx->slots, 256, 8192), 256, 0, ctx->stream>>>(
+        ctx->slots, ctx->px, ctx->py, ctx->pz, ctx->r0, ctx->rmax);
+    LAUNCH_CHECK(ctx);
+    ctx->deph = true;
+    return PIC_OK;
+}
+
+pic_status pic_dephasing_read(pic_ctx *ctx, pic_mem mem, double *R0, double *rmax)
+{
+    CTX_CHECK(ctx);
+    if (mem != PIC_MEM_HOST && mem != PIC_MEM_DEVICE) return fail(ctx, PIC_E_ARG, "bad pic_mem");
+    if (!ctx->r0) return fail(ctx, PIC_E_STATE, "the dephasing diagnostic was never switched on");
+    const size_t n = size_t(ctx->np);
+    if (n == 0 || (!R0 && !rmax)) return PIC_OK;
+    const int grid = grid_for(ctx->slots, 256, 8192);
+    if (mem == PIC_MEM_DEVICE) {
+        dephasing_read_kernel<<<grid, 256, 0, ctx->stream>>>(ctx->perm, ctx->slots, ctx->r0,
+                                                             ctx->rmax, R0, rmax);
+        LAUNCH_CHECK(ctx);
+        return PIC_OK;
+    }
+    double *d = nullptr;
+    pic_status st = dev_alloc(ctx, &d, 2 * n);
+    if (st) return st;
+    dephasing_read_kernel<<<grid, 256, 0, ctx->stream>>>(ctx->perm, ctx->slots, ctx->r0, ctx->rmax,
+                                                         d, d + n);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && R0)
+        e = hipMemcpyAsync(R0, d, n * 8, hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess && rmax)
+        e = hipMemcpyAsync(rmax, d + n, n * 8, hipMemcpyDeviceToHost, ctx->stream);
+    const hipError_t e2 = hipStreamSynchronize(ctx->stream);
+    (void)hipFree(d);
+    if (e != hipSuccess || e2 != hipSuccess)
+        return fail(ctx, PIC_E_DEVICE, "dephasing read: %s",
+                    hipGetErrorString(e != hipSuccess ? e : e2));
+    return PIC_OK;
+}
+
 pic_status pic_tune_set(pic_ctx *ctx, const pic_tune *t)
 {
     CTX_CHECK(ctx);
@@ -1047,6 +1126,8 @@ pic_status pic_autotune(pic_ctx *ctx, int32_t steps, int32_t reps, pic_tune *bes
     // which the next window fills again before reading
     int8_t *keep_trace = ctx->ktrace;
     ctx->ktrace = nullptr;
+    const bool keep_deph = ctx->deph;
+    ctx->deph = false;
     const pic_tune keep = ctx->tune;
     pic_tune winner = keep;
     double wbest = 1e300;
@@ -1080,6 +1161,7 @@ pic_status pic_autotune(pic_ctx *ctx, int32_t steps, int32_t reps, pic_tune *bes
     for (void *p : ps)
         if (p) (void)hipFree(p);
     ctx->ktrace = keep_trace;
+    ctx->deph = keep_deph;
     ctx->tune = keep;
     if (st) return st;
     if (e != hipSuccess) return fail(ctx, PIC_E_DEVICE, "autotune: %s", hipGetErrorString(e));
@@ -1242,6 +1324,22 @@ pic_status pic_prebin(pic_ctx *ctx, const float *score, int32_t nbuckets, float 
             e = hipMemcpyAsync(soa2[a], nsoa + a * n, n * 8, hipMemcpyDeviceToDevice, ctx->stream);
         if (e == hipSuccess)
             e = hipMemcpyAsync(ctx->kold, nk, n, hipMemcpyDeviceToDevice, ctx->stream);
+        if (e == hipSuccess && ctx->r0) {
+            // the dephasing arrays follow their particles (nsoa is free again;
+            // ctx->perm still holds the old slot map)
+            e = hipMemcpyAsync(nsoa, ctx->r0, n * 8, hipMemcpyDeviceToDevice, ctx->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(nsoa + n, ctx->rmax, n * 8, hipMemcpyDeviceToDevice, ctx->stream);
+            if (e == hipSuccess) {
+                permute_pair_kernel<<<grid_for(slots, 256, 8192), 256, 0, ctx->stream>>>(
+                    dest, slots, ctx->perm, ctx->r0, ctx->rmax, nsoa, nsoa + n);
+                e = hipGetLastError();
+            }
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(ctx->r0, nsoa, n * 8, hipMemcpyDeviceToDevice, ctx->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(ctx->rmax, nsoa + n, n * 8, hipMemcpyDeviceToDevice, ctx->stream);
+        }
         if (e == hipSuccess)
             e = hipMemcpyAsync(ctx->perm, nperm, n * 4, hipMemcpyDeviceToDevice, ctx->stream);
         if (e == hipSuccess)

@@ -121,7 +121,7 @@ __device__ __forceinline__ double comb_lds(const double *p, int field, const W &
     return v;
 }
 
-template <int P, int WPG>
+template <int P, int WPG, bool DEPH = false>
 __global__ void __launch_bounds__(64 * WPG) push_fast_kernel(PushArgs a)
 {
     constexpr int ROWS = 2 * (P + 1);                 // row 2j: E of level j, 2j+1: B
@@ -181,6 +181,12 @@ __global__ void __launch_bounds__(64 * WPG) push_fast_kernel(PushArgs a)
     }
     bool moved = false;
     const bool tracing = a.ktrace != nullptr;
+    constexpr bool deph = DEPH;   // dephasing diagnostic compiled in
+    double r0v = 1.0, rmx = 0.0;
+    if (deph && mine) {
+        r0v = a.r0[s];
+        rmx = a.rmax[s];
+    }
     // launch steps whose k is recorded: [kt_lo, kt_hi)
     int kt_lo = 0, kt_hi = 0;
     if (tracing) {
@@ -383,6 +389,7 @@ __global__ void __launch_bounds__(64 * WPG) push_fast_kernel(PushArgs a)
         }
         cnt.steps_done(done, k);
         cnt.lost += __popcll(wballot(live & !done));
+        if (deph && done) dephasing_update(rmx, r0v, px, py, pz);
 
         // hand the step-ahead window to LDS for the next step
         if (pf_next) {
@@ -408,6 +415,7 @@ __global__ void __launch_bounds__(64 * WPG) push_fast_kernel(PushArgs a)
         }
         a.kold[s] = int8_t(kold);
         a.status[s] = status;
+        if (deph) a.rmax[s] = rmx;
     }
     cnt.flush(a.cnt + (int64_t(run) * NSLOT + pos % NSLOT) * NCNT, lane);
 }

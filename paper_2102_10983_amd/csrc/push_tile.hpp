@@ -25,7 +25,7 @@ namespace picsub {
 
 constexpr int WMAX = 256;   // staged nodes per field level
 
-template <int P, int TILE>
+template <int P, int TILE, bool DEPH = false>
 __global__ void __launch_bounds__(TILE) push_tile_kernel(PushArgs a)
 {
     constexpr int STRIDE = 2 * (P + 1);
@@ -64,6 +64,12 @@ __global__ void __launch_bounds__(TILE) push_tile_kernel(PushArgs a)
     int kold = 0;
     uint8_t status = PIC_PARTICLE_LOST;
     int64_t kt_u = -1;
+    constexpr bool deph = DEPH;   // dephasing diagnostic compiled in
+    double r0v = 1.0, rmx = 0.0;
+    if (deph && mine) {
+        r0v = a.r0[i];
+        rmx = a.rmax[i];
+    }
     if (mine) {
         x = a.x[i];
         px = a.px[i];
@@ -179,6 +185,7 @@ __global__ void __launch_bounds__(TILE) push_tile_kernel(PushArgs a)
                 const double g2 = sqrt(1.0 + ((px * px + py * py) + pz * pz));
                 x = x + R.dt * (px / g2);
                 cnt.step_done(0);
+                if (deph) dephasing_update(rmx, r0v, px, py, pz);
             } else {
                 heavy = true;
                 sx[t] = x;
@@ -269,6 +276,7 @@ __global__ void __launch_bounds__(TILE) push_tile_kernel(PushArgs a)
                 pz = spz[t];
                 if (sst[t] == 0xFF) {
                     cnt.step_done(k);
+                    if (deph) dephasing_update(rmx, r0v, px, py, pz);
                 } else {
                     status = PIC_PARTICLE_LOST;
                     ++cnt.lost;
@@ -284,6 +292,7 @@ __global__ void __launch_bounds__(TILE) push_tile_kernel(PushArgs a)
         a.pz[i] = pz;
         a.kold[i] = int8_t(kold);
         a.status[i] = status;
+        if (deph) a.rmax[i] = rmx;
     }
     flush_wave(cnt, a.cnt + (int64_t(run) * NSLOT + blockIdx.x % NSLOT) * NCNT, lane);
 }

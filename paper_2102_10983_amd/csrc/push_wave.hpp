@@ -22,7 +22,7 @@ namespace picsub {
 
 enum class Arith { IEEE64, FAST64 };
 
-template <int P, int WPG, Arith AR>
+template <int P, int WPG, Arith AR, bool DEPH = false>
 __global__ void __launch_bounds__(64 * WPG) push_wave_kernel(PushArgs a)
 {
     constexpr int STRIDE = 2 * (P + 1);
@@ -69,6 +69,12 @@ __global__ void __launch_bounds__(64 * WPG) push_wave_kernel(PushArgs a)
         }
     }
     bool moved = false;
+    constexpr bool deph = DEPH;   // dephasing diagnostic compiled in
+    double r0v = 1.0, rmx = 0.0;
+    if (deph && mine) {
+        r0v = a.r0[s];
+        rmx = a.rmax[s];
+    }
 
     const int S_run = run_steps(a, R, n0);
     for (int st = 0; st < S_run; ++st) {
@@ -213,6 +219,7 @@ __global__ void __launch_bounds__(64 * WPG) push_wave_kernel(PushArgs a)
         }
         cnt.steps_done(done, k);
         cnt.lost += __popcll(__ballot(live && !done));
+        if (deph && done) dephasing_update(rmx, r0v, px, py, pz);
     }
     if (mine) {
         if (moved) {
@@ -223,6 +230,7 @@ __global__ void __launch_bounds__(64 * WPG) push_wave_kernel(PushArgs a)
         }
         a.kold[s] = int8_t(kold);
         a.status[s] = status;
+        if (deph) a.rmax[s] = rmx;
     }
     cnt.flush(a.cnt + (int64_t(run) * NSLOT + pos % NSLOT) * NCNT, lane);
 }
@@ -244,7 +252,7 @@ __global__ void __launch_bounds__(64 * WPG) push_wave_kernel(PushArgs a)
 // by gamma: this mode trades accuracy (a few 1e-5 at a0 ~ 10..150) for
 // arithmetic width.
 // ---------------------------------------------------------------------
-template <int P, int WPG>
+template <int P, int WPG, bool DEPH = false>
 __global__ void __launch_bounds__(64 * WPG) push_wave_fp32c_kernel(PushArgs a)
 {
     constexpr int STRIDE = 2 * (P + 1);
@@ -283,6 +291,12 @@ __global__ void __launch_bounds__(64 * WPG) push_wave_fp32c_kernel(PushArgs a)
     int kold = 0;
     uint8_t status = PIC_PARTICLE_LOST;
     int64_t kt_u = -1;
+    constexpr bool deph = DEPH;   // dephasing diagnostic compiled in
+    double r0v = 1.0, rmx = 0.0;
+    if (deph && mine) {
+        r0v = a.r0[s];
+        rmx = a.rmax[s];
+    }
     if (mine) {
         const double xi = (a.x[s] - R.x_origin) / R.dx;
         status = a.status[s];
@@ -476,8 +490,12 @@ __global__ void __launch_bounds__(64 * WPG) push_wave_fp32c_kernel(PushArgs a)
         }
         cnt.steps_done(done, k);
         cnt.lost += __popcll(__ballot(live && !done));
+        if (deph && done)
+            dephasing_update(rmx, r0v, double(pxh) + double(pxl), double(pyh) + double(pyl),
+                             double(pzh) + double(pzl));
     }
     if (mine) {
+        if (deph) a.rmax[s] = rmx;
         if (moved) {
             const double xi = double(cell) + (double(fr) + double(frc));
             a.x[s] = R.x_origin + xi * R.dx;

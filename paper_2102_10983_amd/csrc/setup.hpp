@@ -269,4 +269,34 @@ __global__ void diag_kernel(const int32_t *__restrict__ perm, int64_t slots,
     }
 }
 
+// Dephasing diagnostic: R0 = gamma - p_x of the stored momentum of every
+// slot, running maximum reset to zero.
+__global__ void dephasing_init_kernel(int64_t slots, const double *__restrict__ px,
+                                      const double *__restrict__ py,
+                                      const double *__restrict__ pz, double *__restrict__ r0,
+                                      double *__restrict__ rmax)
+{
+    for (int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; s < slots;
+         s += int64_t(gridDim.x) * blockDim.x) {
+        const double a = px[s], b = py[s], c = pz[s];
+        r0[s] = sqrt(1.0 + ((a * a + b * b) + c * c)) - a;
+        rmax[s] = 0.0;
+    }
+}
+
+// R0 and the running maximum in caller order.
+__global__ void dephasing_read_kernel(const int32_t *__restrict__ perm, int64_t slots,
+                                      const double *__restrict__ r0,
+                                      const double *__restrict__ rmax, double *__restrict__ o_r0,
+                                      double *__restrict__ o_rmax)
+{
+    for (int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; s < slots;
+         s += int64_t(gridDim.x) * blockDim.x) {
+        const int32_t u = perm[s];
+        if (u < 0) continue;
+        if (o_r0) o_r0[u] = r0[s];
+        if (o_rmax) o_rmax[u] = rmax[s];
+    }
+}
+
 }  // namespace picsub

@@ -518,3 +518,99 @@ def test_counters_n_and_n_star(orc):
     assert cnt.sub_steps == int(np.sum(4 ** kt.astype(np.int64)))
     assert cnt.n_star == int(np.sum(np.where(kt > 0, 4 ** kt.astype(np.int64), 0)))
     assert list(cnt.steps_by_k)[:9] == [int(np.sum(kt == k)) for k in range(9)]
+
+
+# ---------------------------------------------------------------------------
+# Dephasing diagnostic (Sec. V, Eq. (R error)): R = gamma - p_x is constant
+# along any exact plane-wave trajectory (appendix), so the running maximum
+# of |R - R0| / R0 is zero without fields and vanishes at second order in
+# dt with them
+# ---------------------------------------------------------------------------
+def test_dephasing_zero_without_fields(orc):
+    rng = np.random.default_rng(12)
+    n = 64
+    prm = orc.make_params(256, 3, 0.1, 0.099, 0.01)
+    fs = orc.FieldSource(table=np.zeros(16), M=16, coeffs=(1, 1, 0, 1, 1, 0))
+    st = orc.State(rng.uniform(3.0, 5.0, n), rng.normal(0, 2, n), rng.normal(0, 2, n),
+                   rng.normal(0, 2, n), k_old=np.zeros(n, dtype=np.int8))
+    R0_expect = np.sqrt(1.0 + st.px ** 2 + st.py ** 2 + st.pz ** 2) - st.px
+    R0, rmax, kt = orc.push_dephasing(prm, fs, st, 0, 20)
+    assert np.allclose(R0, R0_expect, rtol=1e-15, atol=0)
+    assert np.all(rmax == 0.0)
+    assert np.all(kt == 0)
+
+
+def test_dephasing_vanishes_at_second_order(orc):
+    """Cold start (R0 = 1) and a warm start (R0 = gamma0 - p_x0) in a flat
+    wave, no sub-cycling: the maximum drops about 16x over two halvings of
+    dt."""
+    for p0 in ((0.0, 0.0, 0.0), (0.3, -0.2, 0.1)):
+        worst = []
+        for n_t in (150, 300, 600):
+            lat = W.yee_lattice(n_t)
+            table, M, shift = W.plane_wave_table(lat, 1.0)
+            fs = orc.FieldSource(table=table, M=M, coeffs=W.shifted_coeffs(lat, shift))
+            prm = orc.make_params(int(14 / lat.dx) + 16, 3, lat.dx, lat.dt, 1e30, lat.x_origin)
+            st = orc.State(np.array([1.3]), [p0[0]], [p0[1]], [p0[2]], k_old=np.array([0]))
+            R0, rmax, _ = orc.push_dephasing(prm, fs, st, 0, 2 * n_t)
+            g0 = math.sqrt(1 + sum(v * v for v in p0))
+            assert R0[0] == pytest.approx(g0 - p0[0], rel=1e-15)
+            worst.append(rmax[0])
+        # two halvings: 16 at second order (a first-order error would give 4)
+        assert 9.0 < worst[0] / worst[2] < 28.0, worst
+        assert worst[-1] < 1e-3
+
+
+def test_dephasing_stops_at_loss(orc):
+    """A particle that leaves the grid keeps the maximum it had reached."""
+    wl = W.make_workload("t", 8, 30.0, 75, 80, 3, 3, 0.01, 0.2, seed=6)
+    table, M, shift = wl.table()
+    fs = orc.FieldSource(table=table, M=M, coeffs=W.shifted_coeffs(wl.lat, shift))
+    prm = orc.make_params(wl.ncells, 3, wl.dx, wl.dt, wl.psi_max, wl.x_origin)
+    st = orc.State(wl.x0)
+    R0, rmax, kt = orc.push_dephasing(prm, fs, st.copy(), 0, wl.steps)
+    lost = np.nonzero(kt[-1] < 0)[0]
+    assert len(lost) > 0
+    for i in lost:
+        s_lost = int(np.argmax(kt[:, i] < 0))           # first step not taken
+        st2 = st.copy()
+        _, rm2, _ = orc.push_dephasing(prm, fs, st2, 0, s_lost)
+        assert rmax[i] == rm2[i]
+
+
+def test_dephasing_in_a_static_magnetic_field(orc):
+    """Uniform static B_z, no E: the Boris step turns p by 2 atan(|q B dt| /
+    (2 gamma)) at constant |p|, so from p = (p0, 0, 0) the running maximum
+    after N steps is max_n p0 (1 - cos(n theta)) / (gamma - p0); R0 far
+    from 1 pins the normalisation."""
+    p0, B0, dt, N = 3.0, 2.0, 0.05, 40
+    g = math.sqrt(1 + p0 * p0)
+    ncells = 4000
+    E, B = _uniform_levels(3, ncells, N + 8, lambda t: 0.0 * t, lambda t: B0 + 0.0 * t, dt)
+    fs = _explicit_fields(E, B, lev0=-3)
+    prm = orc.make_params(ncells, 3, 0.1, dt, 1e30)
+    st = orc.State(np.array([20.0]), [p0], [0.0], [0.0], k_old=np.array([0]))
+    R0, rmax, kt = orc.push_dephasing(prm, fs, st, 0, N)
+    theta = 2 * math.atan(B0 * dt / (2 * g))
+    want = max(p0 * (1 - math.cos(n * theta)) for n in range(1, N + 1)) / (g - p0)
+    assert R0[0] == pytest.approx(g - p0, rel=1e-14)
+    assert rmax[0] == pytest.approx(want, rel=1e-9)
+    assert want > 10.0
+
+
+def test_dephasing_ignores_a_step_cut_short(orc):
+    """A sub-cycled particle that leaves the grid half-way through its first
+    step has completed no step: its maximum stays 0 although its momentum
+    has turned."""
+    dt, dx, B0 = 2 * math.pi / 75, 1.01 * 2 * math.pi / 75, 10.0
+    ncells = 64
+    E, B = _uniform_levels(3, ncells, 12, lambda t: 0.0 * t, lambda t: B0 + 0.0 * t, dt)
+    fs = _explicit_fields(E, B, lev0=-3)
+    prm = orc.make_params(ncells, 3, dx, dt, 0.01)
+    st = orc.State(np.array([(ncells - 1.3) * dx]), [10.0], [0.0], [0.0],
+                   k_old=np.array([0]))
+    R0, rmax, kt = orc.push_dephasing(prm, fs, st, 0, 3)
+    assert kt[0, 0] >= 1                          # sub-cycled ...
+    assert st.status[0] == 1                      # ... and lost during step 0
+    assert st.px[0] != 10.0                       # after turning part of the way
+    assert rmax[0] == 0.0
