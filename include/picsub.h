@@ -117,6 +117,8 @@ typedef struct {
     uint64_t lost;        /* particles flagged lost */
     uint64_t steps_by_k[PIC_KHIST];
     uint64_t sub_steps_by_k[PIC_KHIST];
+    uint64_t rebins;      /* group re-orderings made by an attached predictor
+                             (pic_predictor_set), whole context */
 } pic_counters;
 
 typedef struct pic_ctx pic_ctx;
@@ -422,6 +424,20 @@ pic_status pic_mlp_adam(float *w, float *m, float *v, const float *grad, int32_t
  * (PIC_E_STATE).  Synchronous. */
 pic_status pic_prebin(pic_ctx *ctx, const float *score, int32_t nbuckets, float width,
                       int32_t prio_groups);
+
+/* Attach the predictor to the context, so that the pushes order the work
+ * themselves: before every every_M-th call of pic_push_subcycled (level n)
+ * or pic_advance (each run's level), every particle is scored with the
+ * network (pic_features, pic_mlp_forward) and the groups are re-ordered as
+ * pic_prebin(score, 1 bucket, width) does; the counters' rebins field
+ * counts these.  w_bf16: PIC_MLP_NPARAM BF16 words; norm: 2 *
+ * PIC_MLP_FEATURES floats; run_a0: one a0 > 0 per run (host arrays,
+ * copied).  The features need level n - 2 in the ring (always there for
+ * order >= 2).  Each turn synchronises the stream; windows captured into a
+ * graph run without it (they keep whatever order is current when they
+ * run).  w_bf16 == NULL detaches.  Results never depend on it. */
+pic_status pic_predictor_set(pic_ctx *ctx, const uint16_t *w_bf16, const float *norm,
+                             const float *run_a0, float width, int32_t every_M);
 
 #ifdef __cplusplus
 }

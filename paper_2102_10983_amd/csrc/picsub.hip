@@ -80,6 +80,14 @@ struct pic_ctx {
     int32_t ngroups = 0;
     double *wtab = nullptr;
     uint64_t *cnt = nullptr;
+    // attached load predictor (pic_predictor_set)
+    uint16_t *pred_w = nullptr;
+    float *pred_norm = nullptr, *pred_feat = nullptr, *pred_score = nullptr;
+    std::vector<float> pred_a0;
+    float pred_width = 0.0625f;
+    int32_t pred_every = 0;
+    int64_t pred_calls = 0;
+    uint64_t rebins = 0;
     // dephasing diagnostic (allocated when first switched on)
     double *r0 = nullptr, *rmax = nullptr;
     bool deph = false;
@@ -148,7 +156,7 @@ void free_all(pic_ctx *c)
     c->graph = nullptr;
     void *ptrs[] = {c->x, c->px, c->py, c->pz, c->kold, c->status, c->perm, c->key,
                     c->d_runs, c->group_run, c->group_order, c->group_prio, c->wtab, c->cnt,
-                    c->r0, c->rmax};
+                    c->r0, c->rmax, c->pred_w, c->pred_norm, c->pred_feat, c->pred_score};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (RunHost &r : c->runs) {
@@ -165,6 +173,9 @@ void free_all(pic_ctx *c)
     c->cnt = nullptr;
     c->r0 = c->rmax = nullptr;
     c->deph = false;
+    c->pred_w = nullptr;
+    c->pred_norm = c->pred_feat = c->pred_score = nullptr;
+    c->pred_every = 0;
 }
 
 pic_status check_params(pic_ctx *ctx, const pic_params *p, int64_t np, int r)
@@ -400,6 +411,26 @@ pic_status read_counters(pic_ctx *ctx, int32_t run, pic_counters *cnt)
         cnt->sub_steps += sub;
         if (k > 0) cnt->n_star += sub;
     }
+    cnt->rebins = ctx->rebins;
+    return PIC_OK;
+}
+
+// The attached predictor before a push: every pred_every-th call scores
+// every particle at level n (NO_LEVEL: each run's device-driven level) and
+// re-orders the groups, heaviest first (one bucket: particles keep their
+// slots).  Synchronises the stream.
+pic_status predictor_turn(pic_ctx *ctx, int64_t n)
+{
+    if (!ctx->pred_w || ctx->pred_every <= 0) return PIC_OK;
+    if (ctx->pred_calls++ % ctx->pred_every != 0) return PIC_OK;
+    pic_status st = pic_features(ctx, n, ctx->pred_a0.data(), ctx->pred_feat);
+    if (st) return st;
+    st = pic_mlp_forward(ctx->pred_w, ctx->pred_norm, ctx->pred_feat, ctx->pred_score, ctx->np,
+                         ctx->stream);
+    if (st) return fail(ctx, st, "predictor forward pass failed");
+    st = pic_prebin(ctx, ctx->pred_score, 1, ctx->pred_width, 0);
+    if (st) return st;
+    ++ctx->rebins;
     return PIC_OK;
 }
 
@@ -603,6 +634,7 @@ pic_status load_particles(pic_ctx *ctx, pic_mem mem, const double *x, const doub
     }
     if (e == hipSuccess)
         e = hipMemsetAsync(ctx->cnt, 0, cnt_words(ctx) * sizeof(uint64_t), ctx->stream);
+    ctx->rebins = 0;
     if (e == hipSuccess)
         e = hipMemsetAsync(ctx->group_prio, 0, size_t(ctx->ngroups), ctx->stream);
     if (e == hipSuccess) {
@@ -772,6 +804,7 @@ pic_status pic_advance(pic_ctx *ctx, int32_t S)
     CTX_CHECK(ctx);
     pic_status st = check_window(ctx, S);
     if (st) return st;
+    if (ctx->np > 0 && (st = predictor_turn(ctx, NO_LEVEL))) return st;
     if (ctx->np > 0 && (st = enqueue_window(ctx, S, ctx->stream))) return st;
     if (ctx->np == 0) {
         // nothing to push, but the device-side levels move on as well
@@ -881,6 +914,8 @@ pic_status pic_push_subcycled(pic_ctx *ctx, int64_t n, int32_t S)
                             (long long)m);
     }
     if (ctx->np == 0) return PIC_OK;
+    const pic_status st = predictor_turn(ctx, n);
+    if (st) return st;
     return launch_push(ctx, n, S, ctx->stream);
 }
 
@@ -888,6 +923,7 @@ pic_status pic_counters_reset(pic_ctx *ctx)
 {
     CTX_CHECK(ctx);
     HIP_TRY(ctx, hipMemsetAsync(ctx->cnt, 0, cnt_words(ctx) * sizeof(uint64_t), ctx->stream));
+    ctx->rebins = 0;
     return PIC_OK;
 }
 
@@ -948,6 +984,45 @@ pic_status pic_diag(pic_ctx *ctx, pic_mem mem, double *gamma, double *px, double
         }
     }
     if (cnt) return read_counters(ctx, -1, cnt);
+    return PIC_OK;
+}
+
+pic_status pic_predictor_set(pic_ctx *ctx, const uint16_t *w_bf16, const float *norm,
+                             const float *run_a0, float width, int32_t every_M)
+{
+    CTX_CHECK(ctx);
+    if (!w_bf16) {                 // detach
+        ctx->pred_every = 0;
+        return PIC_OK;
+    }
+    if (!norm || !run_a0) return fail(ctx, PIC_E_ARG, "null normalisation or a0 array");
+    if (every_M < 1) return fail(ctx, PIC_E_ARG, "every_M must be >= 1");
+    if (!(width > 0.0f)) return fail(ctx, PIC_E_ARG, "width must be > 0");
+    for (int r = 0; r < ctx->nruns; ++r)
+        if (!(run_a0[r] > 0.0f)) return fail(ctx, PIC_E_ARG, "run %d: a0 must be > 0", r);
+    const size_t np = size_t(std::max<int64_t>(ctx->np, 1));
+    pic_status st;
+    if (!ctx->pred_w &&
+        ((st = dev_alloc(ctx, &ctx->pred_w, size_t(PIC_MLP_NPARAM))) ||
+         (st = dev_alloc(ctx, &ctx->pred_norm, size_t(2 * PIC_MLP_FEATURES))) ||
+         (st = dev_alloc(ctx, &ctx->pred_feat, np * PIC_MLP_FEATURES)) ||
+         (st = dev_alloc(ctx, &ctx->pred_score, np)))) {
+        void *ps[] = {ctx->pred_w, ctx->pred_norm, ctx->pred_feat, ctx->pred_score};
+        for (void *q : ps)
+            if (q) (void)hipFree(q);
+        ctx->pred_w = nullptr;
+        ctx->pred_norm = ctx->pred_feat = ctx->pred_score = nullptr;
+        return st;
+    }
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->pred_w, w_bf16, PIC_MLP_NPARAM * sizeof(uint16_t),
+                                hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->pred_norm, norm, 2 * PIC_MLP_FEATURES * sizeof(float),
+                                hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->pred_a0.assign(run_a0, run_a0 + ctx->nruns);
+    ctx->pred_width = width;
+    ctx->pred_every = every_M;
+    ctx->pred_calls = 0;
     return PIC_OK;
 }
 
@@ -1408,6 +1483,7 @@ struct CkptRun {
     int32_t order;
 };
 constexpr char CKPT_MAGIC[8] = {'P', 'I', 'C', 'S', 'U', 'B', 'C', 'K'};
+constexpr uint32_t CKPT_VERSION = 2;   // 2: pic_counters carries rebins
 
 size_t ckpt_bytes(const pic_ctx *ctx)
 {
@@ -1438,7 +1514,7 @@ pic_status pic_state_export(pic_ctx *ctx, void *buf, size_t *bytes)
     char *o = static_cast<char *>(buf);
     CkptHeader h{};
     std::memcpy(h.magic, CKPT_MAGIC, 8);
-    h.version = 1;
+    h.version = CKPT_VERSION;
     h.nruns = ctx->nruns;
     h.np = ctx->np;
     std::memcpy(o, &h, sizeof h);
@@ -1478,7 +1554,7 @@ pic_status pic_state_import(pic_ctx *ctx, const void *buf, size_t bytes, int64_t
     CkptHeader h;
     std::memcpy(&h, i, sizeof h);
     i += sizeof h;
-    if (std::memcmp(h.magic, CKPT_MAGIC, 8) != 0 || h.version != 1)
+    if (std::memcmp(h.magic, CKPT_MAGIC, 8) != 0 || h.version != CKPT_VERSION)
         return fail(ctx, PIC_E_ARG, "not a checkpoint of this library");
     if (h.nruns != ctx->nruns || h.np != ctx->np || bytes < need)
         return fail(ctx, PIC_E_ARG, "checkpoint of %d runs / %lld particles, context has %d / %lld",
@@ -1523,6 +1599,7 @@ pic_status pic_state_import(pic_ctx *ctx, const void *buf, size_t bytes, int64_t
     }
     HIP_TRY(ctx, hipMemcpyAsync(ctx->cnt, w.data(), w.size() * sizeof(uint64_t),
                                 hipMemcpyHostToDevice, ctx->stream));
+    ctx->rebins = cs.empty() ? 0 : cs[0].rebins;
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     if (levels)
         for (int r = 0; r < ctx->nruns; ++r) levels[r] = lev[size_t(r)];

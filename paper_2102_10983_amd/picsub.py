@@ -33,7 +33,8 @@ EXPORTS = ("pic_create", "pic_destroy", "pic_last_error", "pic_particles_set",
            "pic_group_count", "pic_order_set", "pic_features", "pic_mlp_forward",
            "pic_mlp_grad", "pic_mlp_adam", "pic_prebin", "pic_state_export",
            "pic_state_import", "pic_fields_yee", "pic_fields_yee_r", "pic_fields_read",
-           "pic_fields_read_r", "pic_dephasing_track", "pic_dephasing_read")
+           "pic_fields_read_r", "pic_dephasing_track", "pic_dephasing_read",
+           "pic_predictor_set")
 
 MLP_FEATURES = 8
 MLP_HIDDEN = 64
@@ -58,13 +59,13 @@ class Counters(C.Structure):
     _fields_ = [("steps", C.c_uint64), ("sub_steps", C.c_uint64), ("n_star", C.c_uint64),
                 ("clamps", C.c_uint64), ("lost", C.c_uint64),
                 ("steps_by_k", C.c_uint64 * PIC_KHIST),
-                ("sub_steps_by_k", C.c_uint64 * PIC_KHIST)]
+                ("sub_steps_by_k", C.c_uint64 * PIC_KHIST), ("rebins", C.c_uint64)]
 
     def as_dict(self):
         return {"steps": self.steps, "sub_steps": self.sub_steps, "n_star": self.n_star,
                 "clamps": self.clamps, "lost": self.lost,
                 "steps_by_k": list(self.steps_by_k),
-                "sub_steps_by_k": list(self.sub_steps_by_k)}
+                "sub_steps_by_k": list(self.sub_steps_by_k), "rebins": self.rebins}
 
 
 class Tune(C.Structure):
@@ -131,6 +132,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "pic_fields_read": ([vp, i64, C.c_int, vp, vp], C.c_int),
         "pic_fields_read_r": ([vp, i32, i64, C.c_int, vp, vp], C.c_int),
         "pic_dephasing_track": ([vp, i32], C.c_int),
+        "pic_predictor_set": ([vp, vp, vp, vp, C.c_float, i32], C.c_int),
         "pic_dephasing_read": ([vp, C.c_int, vp, vp], C.c_int),
     }
     for name, (args, res) in sig.items():
@@ -300,6 +302,24 @@ class Pusher:
         self._check(self._lib.pic_fields_read_r(self._ctx, run, n, MEM_HOST, E.ctypes.data,
                                                 B.ctypes.data))
         return E, B
+
+    def predictor_set(self, w_bf16=None, norm=None, run_a0=None, width: float = 0.0625,
+                      every: int = 1):
+        """Attach a predictor (host arrays: BF16 words as uint16, norm, one
+        a0 per run); the pushes then re-order the groups every `every`-th
+        call.  No arguments: detach."""
+        if w_bf16 is None:
+            self._check(self._lib.pic_predictor_set(self._ctx, None, None, None, 0.0, 0))
+            return
+        w = np.ascontiguousarray(w_bf16, dtype=np.uint16)
+        nm = np.ascontiguousarray(norm, dtype=np.float32)
+        a0 = np.ascontiguousarray(np.broadcast_to(np.asarray(run_a0, dtype=np.float32),
+                                                  (self.nruns,)))
+        if w.size != MLP_NPARAM or nm.size != 2 * MLP_FEATURES:
+            raise ValueError("wrong weight or normalisation size")
+        self._keep_pred = (w, nm, a0)
+        self._check(self._lib.pic_predictor_set(self._ctx, w.ctypes.data, nm.ctypes.data,
+                                                a0.ctypes.data, float(width), int(every)))
 
     def dephasing_track(self, on: bool = True):
         """Start (restart) or stop the running max of |R - R0| / R0, R = gamma - p_x."""

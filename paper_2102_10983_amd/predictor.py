@@ -79,6 +79,11 @@ class Predictor:
         """Predicted log2 load of every particle of `pusher` at level n."""
         return self.predict(pusher.features(a0, n=n))
 
+    def attach(self, pusher: picsub.Pusher, a0, every: int = 1, width: float = 0.0625):
+        """Let the pushes of `pusher` score and re-order by themselves
+        (pic_predictor_set) every `every`-th push call."""
+        pusher.predictor_set(_bf16_bits(self.w), self.norm, a0, width=width, every=every)
+
     def prebin(self, pusher: picsub.Pusher, a0, n=None, nbuckets: int = 1, width: float = 0.0625,
                prio_groups: int = 0):
         """Score the particles and re-bin / re-order the groups."""
