@@ -202,6 +202,8 @@ def main():
     ap.add_argument("--num", type=int, default=0,
                     help="electrons (large: 2^20, stress: 2^24; batch: scale factor x 1e6)")
     ap.add_argument("--periods", type=float, default=100.0)
+    ap.add_argument("--order", type=int, default=3, choices=(1, 3, 5),
+                    help="large/stress: temporal interpolation order p")
     ap.add_argument("--pb-width", type=float, default=0.0625,
                     help="cost step (log2 sub-steps) of the learned group order")
     ap.add_argument("--cpu-every", type=int, default=8)
@@ -231,16 +233,18 @@ def main():
     from paper_2102_10983_amd import predictor as PR, workloads as W
 
     if args.workload == "large":
-        wl = W.large_case(seed=args.seed, num=args.num or (1 << 20), periods=args.periods)
+        wl = W.large_case(seed=args.seed, num=args.num or (1 << 20), periods=args.periods,
+                          order=args.order)
         steps_max = wl.steps
         wdesc = (f"plane wave a0={wl.a0:g}, {wl.num} electrons at rest over 8 lambda, T/dt=75, "
                  f"dx=1.01 c dt, {wl.ncells} cells, {wl.steps} steps, order {wl.order}, "
                  f"psi_max {wl.psi_max}")
     elif args.workload == "stress":
-        wl = W.stress_case(psi_max=args.psi, num=args.num or (1 << 24), periods=args.periods)
+        wl = W.stress_case(psi_max=args.psi, num=args.num or (1 << 24), periods=args.periods,
+                           order=args.order)
         steps_max = wl.steps
         wdesc = (f"plane wave a0=150, {wl.num} thermal (10 keV) electrons over 200 lambda, "
-                 f"T/dt=75, {wl.ncells} cells, {wl.steps} steps, order 3, psi_max {wl.psi_max}")
+                 f"T/dt=75, {wl.ncells} cells, {wl.steps} steps, order {wl.order}, psi_max {wl.psi_max}")
     else:
         scale = (args.num / 1e6) if args.num else 1.0
         wl = W.batch_case(seed=3, nruns=64, periods=50.0, scale=scale)
@@ -272,7 +276,7 @@ def main():
     achieved = flops_step * args.steps / (kernel_ms / 1e3) / 1e12
     key = "ballot" if args.binning == "ballot" else args.precision
     traffic = (measured_traffic(key, launches_per_step)
-               if args.workload == "large" and args.fields == "lattice" else None)
+               if args.workload == "large" and args.fields == "lattice" and order == 3 else None)
     solve_ms = (sum(a.elapsed_time(b) for a, b in main_pass.fill_events) / args.steps
                 if args.fields == "yee" else None)
 
@@ -327,7 +331,7 @@ def main():
         "compare": compare,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
-                     "kernel": KERNELS[key][0], "launches": launches,
+                     "kernel": KERNELS[key][0].replace("<3,", f"<{order},"), "launches": launches,
                      "avg_launch_ms": kernel_ms / launches,
                      "flops_per_launch": flops_step * args.steps / launches},
     }

@@ -182,7 +182,7 @@ typedef struct {
 static int one_step(const orc_params *prm, const orc_fields *f, int64_t n,
                     double *x, double *px, double *py, double *pz,
                     int8_t *k_old, int forced, int32_t *k_out,
-                    double *psi_ratio, local_cnt *lc)
+                    double *psi_ratio, double *step_work, local_cnt *lc)
 {
     double LE[ORC_MAX_ORDER + 1], LB[ORC_MAX_ORDER + 1];
     double Ep, Bp;
@@ -221,7 +221,15 @@ static int one_step(const orc_params *prm, const orc_fields *f, int64_t n,
         orc_lagrange(prm->order, s, LE, LB);
         if ((rc = tent(prm, f, 0, n, xi, LE, &Ep))) return rc;
         if ((rc = tent(prm, f, 1, n, xi, LB, &Bp))) return rc;
+        /* work of E over the sub-step (App. B): q dt_p / 2 E . (v_before +
+         * v_after); E has only a y component here */
+        double vb = 0.0;
+        if (step_work) vb = *py / sqrt(1.0 + ((*px * *px + *py * *py) + *pz * *pz));
         orc_boris(prm->qm, dtp, Ep, Bp, px, py, pz);
+        if (step_work) {
+            double ga = sqrt(1.0 + ((*px * *px + *py * *py) + *pz * *pz));
+            *step_work += ((0.5 * prm->qm) * dtp * Ep) * (vb + *py / ga);
+        }
         *x = advance_x(*x, dt_new, *px, *py, *pz);
     }
     /* a step is counted once all its sub-steps are done */
@@ -245,7 +253,7 @@ int orc_push(const orc_params *prm, const orc_fields *f, int64_t np,
              double *x, double *px, double *py, double *pz,
              int8_t *k_old, uint8_t *status, int64_t n0, int32_t nsteps,
              const int8_t *forced_k, int8_t *k_trace, double *psi_trace,
-             orc_counters *cnt, int32_t nthreads)
+             double *work, double *werr, orc_counters *cnt, int32_t nthreads)
 {
     if (!prm || !f || np < 0 || nsteps < 0) return -1;
     if (prm->order < 1 || prm->order > ORC_MAX_ORDER) return -1;
@@ -279,10 +287,20 @@ int orc_push(const orc_params *prm, const orc_fields *f, int64_t np,
                 int32_t k = -1;
                 double ratio = -1.0;
                 int forced = forced_k ? (int)forced_k[tix] : -1;
+                double g_start = sqrt(1.0 + ((px[i] * px[i] + py[i] * py[i]) + pz[i] * pz[i]));
+                double sw = 0.0;
                 int rc = one_step(prm, f, n0 + st, &x[i], &px[i], &py[i],
-                                  &pz[i], &k_old[i], forced, &k, &ratio, &lc);
+                                  &pz[i], &k_old[i], forced, &k, &ratio,
+                                  (work || werr) ? &sw : NULL, &lc);
                 if (k_trace) k_trace[tix] = (int8_t)k;
                 if (psi_trace) psi_trace[tix] = ratio;
+                if (rc == 0 && (work || werr)) {
+                    /* a completed step: kinetic energy change against work */
+                    double g_end = sqrt(1.0 + ((px[i] * px[i] + py[i] * py[i]) + pz[i] * pz[i]));
+                    double d = fabs((g_end - g_start) - sw);
+                    if (work) work[i] += sw;
+                    if (werr && d > werr[i]) werr[i] = d;
+                }
                 if (rc == 1) {
                     status[i] = ORC_LOST;
                     lc.lost += 1;

@@ -111,6 +111,11 @@ void orc_boris(double qm, double dtp, double E, double B,
 
 /* Advance np particles over nsteps steps of size dt starting at level n0
  * (x at n0 dt on entry, at (n0+nsteps) dt on exit).
+ * work and werr (np each, may be NULL): after every completed step, the
+ * work of E over its sub-steps (App. B: q dt_p / 2 E . (v_before +
+ * v_after) per sub-step) is added to work[i], and werr[i] keeps the
+ * largest |(gamma_end - gamma_start) - step work| (kinetic energy change
+ * against work, in m c^2).
  * k_old[i] < 0 means "no previous sub-step": the first transition push
  * then uses dt*_new.  forced_k ([nsteps][np], may be NULL) replaces the
  * decision; k_trace and psi_trace ([nsteps][np], may be NULL) record the
@@ -121,7 +126,7 @@ int orc_push(const orc_params *prm, const orc_fields *f, int64_t np,
              double *x, double *px, double *py, double *pz,
              int8_t *k_old, uint8_t *status, int64_t n0, int32_t nsteps,
              const int8_t *forced_k, int8_t *k_trace, double *psi_trace,
-             orc_counters *cnt, int32_t nthreads);
+             double *work, double *werr, orc_counters *cnt, int32_t nthreads);
 
 /* number of OpenMP threads the library would use */
 int32_t orc_max_threads(void);

@@ -76,7 +76,7 @@ def lib():
                                C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                C.c_void_p, C.c_void_p, C.c_int64, C.c_int32,
                                C.c_void_p, C.c_void_p, C.c_void_p,
-                               C.POINTER(Counters), C.c_int32]
+                               C.c_void_p, C.c_void_p, C.POINTER(Counters), C.c_int32]
         L.orc_push.restype = C.c_int
         L.orc_max_threads.restype = C.c_int32
         _lib = L
@@ -174,8 +174,13 @@ class State:
 
 def push(prm: Params, fs: FieldSource, st: State, n0: int, nsteps: int, *,
          forced_k=None, trace=False, psi_trace=False, counters: Counters | None = None,
-         threads: int = 0):
-    """Advance the state in place; returns (k_trace, psi_trace) arrays or None."""
+         threads: int = 0, work=None, werr=None):
+    """Advance the state in place; returns (k_trace, psi_trace) arrays or None.
+    work, werr: float64 arrays of st.num updated in place (App. B energy
+    accounting, see orc_push)."""
+    for a in (work, werr):
+        if a is not None:
+            assert a.dtype == np.float64 and a.shape == (st.num,) and a.flags.c_contiguous
     kt = np.empty((nsteps, st.num), dtype=np.int8) if trace else None
     pt = np.empty((nsteps, st.num), dtype=np.float64) if psi_trace else None
     fk = None if forced_k is None else np.ascontiguousarray(forced_k, dtype=np.int8)
@@ -184,7 +189,8 @@ def push(prm: Params, fs: FieldSource, st: State, n0: int, nsteps: int, *,
     cnt = counters if counters is not None else Counters()
     rc = lib().orc_push(C.byref(prm), C.byref(fs.s), st.num, _ptr(st.x), _ptr(st.px),
                         _ptr(st.py), _ptr(st.pz), _ptr(st.k_old), _ptr(st.status),
-                        n0, nsteps, _ptr(fk), _ptr(kt), _ptr(pt), C.byref(cnt), threads)
+                        n0, nsteps, _ptr(fk), _ptr(kt), _ptr(pt), _ptr(work), _ptr(werr),
+                        C.byref(cnt), threads)
     if rc != 0:
         raise ValueError(f"orc_push failed ({rc})")
     return kt, pt
@@ -198,26 +204,29 @@ def dephasing_R(px, py, pz):
     return np.sqrt(1.0 + ((px * px + py * py) + pz * pz)) - px
 
 
-def push_dephasing(prm: Params, fs: FieldSource, st: State, n0: int, nsteps: int, *,
-                   forced_k=None, counters: Counters | None = None, threads: int = 0):
+def push_diagnostics(prm: Params, fs: FieldSource, st: State, n0: int, nsteps: int, *,
+                     forced_k=None, counters: Counters | None = None, threads: int = 0):
     """push() one step at a time, recording after every completed step of a
     live particle the dephasing error |R - R0| / R0 of Eq. (R error), R0
-    being R of the state passed in; returns (R0, the running maximum, the k
-    trace [nsteps, num])."""
+    being R of the state passed in, and the energy accounting of App. B.
+    Returns (R0, running max of the dephasing error, work since the start,
+    largest per-step |kinetic energy change - work|, k trace [nsteps, num])."""
     R0 = dephasing_R(st.px, st.py, st.pz)
     rmax = np.zeros(st.num)
+    work = np.zeros(st.num)
+    werr = np.zeros(st.num)
     kt = np.empty((nsteps, st.num), dtype=np.int8)
     cnt = counters if counters is not None else Counters()
     for c in range(nsteps):
         live_before = st.status == 0
         fk = None if forced_k is None else np.ascontiguousarray(forced_k[c:c + 1])
         k1, _ = push(prm, fs, st, n0 + c, 1, forced_k=fk, trace=True, counters=cnt,
-                     threads=threads)
+                     threads=threads, work=work, werr=werr)
         kt[c] = k1[0]
         done = live_before & (st.status == 0)
         d = np.abs(dephasing_R(st.px, st.py, st.pz) - R0) / R0
         rmax = np.where(done & (d > rmax), d, rmax)
-    return R0, rmax, kt
+    return R0, rmax, work, werr, kt
 
 
 def max_threads() -> int:

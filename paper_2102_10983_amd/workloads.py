@@ -216,11 +216,12 @@ def large_case(seed: int = 22, num: int = 1 << 20, periods: float = 100.0,
                          periods, order, 0.01, 8.0, seed=seed)
 
 
-def stress_case(psi_max: float = 0.01, num: int = 1 << 24, periods: float = 100.0) -> Workload:
+def stress_case(psi_max: float = 0.01, num: int = 1 << 24, periods: float = 100.0,
+                order: int = 3) -> Workload:
     """2^24 thermal electrons (10 keV) over 200 wavelengths, a0 = 150,
-    65536 cells, 3rd order."""
+    65536 cells, 3rd order by default."""
     return make_workload(f"stress psi={psi_max:g} P={num}", num, 150.0, 75, 65536,
-                         periods, 3, psi_max, 200.0, seed=5, theta=10.0 / 511.0)
+                         periods, order, psi_max, 200.0, seed=5, theta=10.0 / 511.0)
 
 
 def batch_case(seed: int = 3, nruns: int = 64, periods: float = 50.0,

@@ -4,7 +4,7 @@ kernel when switched on.
 
 * PIC_FP64 (wavefront and ballot kernels, one launch and chunks of 16):
   R0 and the maximum bit-identical to the FP64 oracle stepping one step at
-  a time (oracle.push_dephasing).
+  a time (oracle.push_diagnostics).
 * PIC_FP64_FAST: within the bound the 1e-5 bar on p implies,
   |d(R / R0)| <= 2 * 1e-5 * max|p| / R0, on electrons whose k sequence
   matches the oracle's (others are replayed with the device's k).
@@ -56,7 +56,9 @@ def _oracle(wl, fields=None, forced_k=None, idx=None):
     idx = np.arange(wl.num) if idx is None else idx
     st = O.State(wl.x0[idx], wl.p0[0][idx], wl.p0[1][idx], wl.p0[2][idx])
     fs = oracle_fields(wl) if fields is None else fields
-    return O.push_dephasing(oracle_params(wl), fs, st, 0, wl.steps, forced_k=forced_k) + (st,)
+    R0, rmax, _, _, kt = O.push_diagnostics(oracle_params(wl), fs, st, 0, wl.steps,
+                                             forced_k=forced_k)
+    return R0, rmax, kt, st
 
 
 @pytest.mark.parametrize("S,binning", [(1500, "none"), (16, "none"), (16, "ballot")])

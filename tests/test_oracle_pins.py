@@ -534,7 +534,7 @@ def test_dephasing_zero_without_fields(orc):
     st = orc.State(rng.uniform(3.0, 5.0, n), rng.normal(0, 2, n), rng.normal(0, 2, n),
                    rng.normal(0, 2, n), k_old=np.zeros(n, dtype=np.int8))
     R0_expect = np.sqrt(1.0 + st.px ** 2 + st.py ** 2 + st.pz ** 2) - st.px
-    R0, rmax, kt = orc.push_dephasing(prm, fs, st, 0, 20)
+    R0, rmax, _, _, kt = orc.push_diagnostics(prm, fs, st, 0, 20)
     assert np.allclose(R0, R0_expect, rtol=1e-15, atol=0)
     assert np.all(rmax == 0.0)
     assert np.all(kt == 0)
@@ -552,7 +552,7 @@ def test_dephasing_vanishes_at_second_order(orc):
             fs = orc.FieldSource(table=table, M=M, coeffs=W.shifted_coeffs(lat, shift))
             prm = orc.make_params(int(14 / lat.dx) + 16, 3, lat.dx, lat.dt, 1e30, lat.x_origin)
             st = orc.State(np.array([1.3]), [p0[0]], [p0[1]], [p0[2]], k_old=np.array([0]))
-            R0, rmax, _ = orc.push_dephasing(prm, fs, st, 0, 2 * n_t)
+            R0, rmax, _, _, _ = orc.push_diagnostics(prm, fs, st, 0, 2 * n_t)
             g0 = math.sqrt(1 + sum(v * v for v in p0))
             assert R0[0] == pytest.approx(g0 - p0[0], rel=1e-15)
             worst.append(rmax[0])
@@ -568,13 +568,13 @@ def test_dephasing_stops_at_loss(orc):
     fs = orc.FieldSource(table=table, M=M, coeffs=W.shifted_coeffs(wl.lat, shift))
     prm = orc.make_params(wl.ncells, 3, wl.dx, wl.dt, wl.psi_max, wl.x_origin)
     st = orc.State(wl.x0)
-    R0, rmax, kt = orc.push_dephasing(prm, fs, st.copy(), 0, wl.steps)
+    R0, rmax, _, _, kt = orc.push_diagnostics(prm, fs, st.copy(), 0, wl.steps)
     lost = np.nonzero(kt[-1] < 0)[0]
     assert len(lost) > 0
     for i in lost:
         s_lost = int(np.argmax(kt[:, i] < 0))           # first step not taken
         st2 = st.copy()
-        _, rm2, _ = orc.push_dephasing(prm, fs, st2, 0, s_lost)
+        _, rm2, _, _, _ = orc.push_diagnostics(prm, fs, st2, 0, s_lost)
         assert rmax[i] == rm2[i]
 
 
@@ -590,12 +590,14 @@ def test_dephasing_in_a_static_magnetic_field(orc):
     fs = _explicit_fields(E, B, lev0=-3)
     prm = orc.make_params(ncells, 3, 0.1, dt, 1e30)
     st = orc.State(np.array([20.0]), [p0], [0.0], [0.0], k_old=np.array([0]))
-    R0, rmax, kt = orc.push_dephasing(prm, fs, st, 0, N)
+    R0, rmax, work, werr, kt = orc.push_diagnostics(prm, fs, st, 0, N)
     theta = 2 * math.atan(B0 * dt / (2 * g))
     want = max(p0 * (1 - math.cos(n * theta)) for n in range(1, N + 1)) / (g - p0)
     assert R0[0] == pytest.approx(g - p0, rel=1e-14)
     assert rmax[0] == pytest.approx(want, rel=1e-9)
     assert want > 10.0
+    # no E: no work; the rotation keeps gamma up to rounding
+    assert work[0] == 0.0 and werr[0] < 1e-13
 
 
 def test_dephasing_ignores_a_step_cut_short(orc):
@@ -609,8 +611,54 @@ def test_dephasing_ignores_a_step_cut_short(orc):
     prm = orc.make_params(ncells, 3, dx, dt, 0.01)
     st = orc.State(np.array([(ncells - 1.3) * dx]), [10.0], [0.0], [0.0],
                    k_old=np.array([0]))
-    R0, rmax, kt = orc.push_dephasing(prm, fs, st, 0, 3)
+    R0, rmax, work, werr, kt = orc.push_diagnostics(prm, fs, st, 0, 3)
     assert kt[0, 0] >= 1                          # sub-cycled ...
     assert st.status[0] == 1                      # ... and lost during step 0
     assert st.px[0] != 10.0                       # after turning part of the way
-    assert rmax[0] == 0.0
+    assert rmax[0] == 0.0 and work[0] == 0.0 and werr[0] == 0.0
+
+
+
+# ---------------------------------------------------------------------------
+# Energy accounting (App. B): work of E per sub-step q dt_p / 2 E . (v_before
+# + v_after) against the change of gamma over each completed step
+# ---------------------------------------------------------------------------
+def test_energy_uniform_electric_field_third_order(orc):
+    """Uniform static E_y, no B, from rest: p_y grows by q E dt per step
+    (exact), the trapezoidal work differs from the exact change of gamma by
+    O(dt^3) per step: halving dt divides the largest step error by ~8, and
+    the work adds up to the kinetic energy gained."""
+    E0, T = 1.5, 3.0
+    errs = []
+    for dt in (0.1, 0.05, 0.025):
+        n = int(round(T / dt))
+        E, B = _uniform_levels(1, 400, n + 6, lambda t: E0 + 0.0 * t, lambda t: 0.0 * t, dt)
+        fs = _explicit_fields(E, B, lev0=-1)
+        prm = orc.make_params(400, 1, 0.5, dt, 1e30)
+        st = orc.State(np.array([100.0]), k_old=np.array([0]))
+        R0, rmax, work, werr, kt = orc.push_diagnostics(prm, fs, st, 0, n)
+        assert st.py[0] == pytest.approx(-E0 * n * dt, rel=1e-12)
+        assert work[0] == pytest.approx(st.gamma()[0] - 1.0, rel=2e-3)
+        assert work[0] > 1.0
+        errs.append(werr[0])
+    assert 6.5 < errs[0] / errs[1] < 9.5 and 6.5 < errs[1] / errs[2] < 9.5, errs
+
+
+def test_energy_plane_wave_work_equals_energy_gain(orc):
+    """App. B: in the plane wave the accumulated work tracks the kinetic
+    energy (gamma - 1) closely, and sub-cycling shrinks the largest
+    per-step mismatch (the stopping points) by orders of magnitude."""
+    def run(psi_max):
+        wl = W.make_workload("t", 16, 100.0, 75, 4096, 8, 3, psi_max, 1.0, seed=9)
+        table, M, shift = wl.table()
+        fs = orc.FieldSource(table=table, M=M, coeffs=W.shifted_coeffs(wl.lat, shift))
+        prm = orc.make_params(wl.ncells, 3, wl.dx, wl.dt, psi_max, wl.x_origin)
+        st = orc.State(wl.x0)
+        _, _, work, werr, _ = orc.push_diagnostics(prm, fs, st, 0, wl.steps)
+        return st.gamma() - 1.0, work, werr, wl
+    ek, work, werr_sub, wl = run(0.01)
+    emax = wl.a0 ** 2 / 2
+    assert np.all(np.abs(ek - work) < 2e-3 * emax)
+    assert np.all(work > -1e-9)
+    _, _, werr_nosub, _ = run(1e30)
+    assert werr_sub.max() < 1e-2 * werr_nosub.max()
