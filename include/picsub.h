@@ -277,29 +277,43 @@ pic_status pic_graph_release(pic_ctx *ctx);
 pic_status pic_run_counters(pic_ctx *ctx, int32_t run, pic_counters *cnt);
 
 /* ------------------------------------------------------------------
- * Dephasing diagnostic (Sec. V, Eq. (R error)).  R = gamma - p_x of the
- * stored momentum is 1 for an electron that starts at rest in a plane
- * wave in vacuum and stays at its initial value R0 for any start (App. A),
- * so max |R - R0| / R0 over a trajectory measures the integrator's error
- * (the paper's epsilon_dephasing when R0 = 1).
+ * Trajectory diagnostics: the paper's two error measures, kept per
+ * particle by every push kernel while switched on.
+ *
+ * Dephasing (Sec. V, Eq. (R error)): R = gamma - p_x of the stored
+ * momentum is 1 for an electron that starts at rest in a plane wave in
+ * vacuum and stays at its initial value R0 for any start (App. A), so the
+ * running maximum of |R - R0| / R0 measures the integrator's error (the
+ * paper's epsilon_dephasing when R0 = 1).
+ *
+ * Energy (App. B): the work of E over each sub-step, q dt_p / 2 E .
+ * (v_before + v_after), summed from the start, and the largest
+ * |(gamma_end - gamma_start) - work| over a single completed step (kinetic
+ * energy in m c^2; the paper normalises it by |q| E0 dt).
  * ------------------------------------------------------------------ */
 
-/* on = 1: (re)start: R0 := R of every particle now, running maximum := 0;
- * from then on every push kernel updates the maximum of |R - R0| / R0
- * after each completed step of a live particle (one square root and one
- * division per particle-step, IEEE, the same in every precision mode).
- * on = 0: stop updating (the values are kept).  Loading particles restarts
- * it while on; re-binning (pic_prebin) carries it with the particles; the
- * autotuner's trials do not touch it; a captured graph keeps the setting
- * it was captured with; checkpoints do not include it. */
-pic_status pic_dephasing_track(pic_ctx *ctx, int32_t on);
+/* on = 1: (re)start: R0 := R of every particle now, maxima and work := 0;
+ * from then on every push kernel updates them after each completed step
+ * of a live particle (a few square roots and divisions per sub-step, IEEE
+ * in the PIC_FP64 kernels, bit-identical to a CPU loop).  on = 0: stop
+ * updating (the values are kept).  Loading particles restarts them while
+ * on; re-binning (pic_prebin) carries them with the particles; the
+ * autotuner's trials do not touch them; a captured graph keeps the setting
+ * it was captured with; checkpoints do not include them.  The kernels
+ * compile them in only while on. */
+pic_status pic_diag_track(pic_ctx *ctx, int32_t on);
 
-/* R0 and the running maximum of every particle in caller order (np
- * doubles each, either may be NULL; host or device memory).
- * PIC_E_STATE if the diagnostic was never switched on.  With
+/* R0 and the running maximum of |R - R0| / R0 of every particle in caller
+ * order (np doubles each, either may be NULL; host or device memory).
+ * PIC_E_STATE if the diagnostics were never switched on.  With
  * PIC_MEM_HOST the call synchronises the stream. */
 pic_status pic_dephasing_read(pic_ctx *ctx, pic_mem mem, double *R0,
                               double *rmax);
+
+/* The work of E since the start and the largest single-step energy
+ * mismatch of every particle, as pic_dephasing_read. */
+pic_status pic_energy_read(pic_ctx *ctx, pic_mem mem, double *work,
+                           double *err_max);
 
 /* ------------------------------------------------------------------ */
 /* Launch shape.  None of these knobs changes a result: every kernel    */

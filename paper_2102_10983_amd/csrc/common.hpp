@@ -48,8 +48,9 @@ struct PushArgs {
     const int32_t *perm;              // slot -> caller index (-1: padding)
     const double *wtab;
     int8_t *ktrace;
-    const double *r0;                 // dephasing diagnostic (null: off): R = gamma - p_x at
-    double *rmax;                     //   the start, running max of |R - R0| / R0
+    const double *r0;                 // trajectory diagnostics (null: off): R = gamma - p_x at
+    double *rmax;                     //   the start, running max of |R - R0| / R0,
+    double *work, *werr;              //   work of E since the start, largest step energy error
     uint64_t *cnt;                    // [nruns][NSLOT][NCNT]
     int64_t kt_n0, kt_first, kt_count;
     int64_t n0;                       // NO_LEVEL: every run starts at its n_cur
@@ -302,12 +303,34 @@ __device__ __forceinline__ int run_steps(const PushArgs &a, const RunDesc &R, in
 // Dephasing diagnostic (Sec. V, Eq. (R error)): after a completed step,
 // R = gamma - p_x of the stored momentum; keep the largest |R - R0| / R0.
 // IEEE square root and division, the order of a CPU loop.
+__device__ __forceinline__ double gamma_of(double px, double py, double pz)
+{
+    return sqrt(1.0 + ((px * px + py * py) + pz * pz));
+}
+
 __device__ __forceinline__ void dephasing_update(double &rmax, double r0, double px, double py,
                                                  double pz)
 {
-    const double g = sqrt(1.0 + ((px * px + py * py) + pz * pz));
-    const double d = fabs((g - px) - r0) / r0;
+    const double d = fabs((gamma_of(px, py, pz) - px) - r0) / r0;
     rmax = d > rmax ? d : rmax;
+}
+
+// Energy accounting (App. B): the work of E over a sub-step is
+// q dt_p / 2 E . (v_before + v_after), with E along y here (c = q dt_p / 2);
+// after a completed step the change of gamma is set against the step's
+// work.  The order of operations is that of a CPU loop.
+__device__ __forceinline__ double sub_step_work(double c, double E, double vy_before,
+                                                double vy_after)
+{
+    return (c * E) * (vy_before + vy_after);
+}
+
+__device__ __forceinline__ void energy_close(double &work, double &werr, double g_start,
+                                             double g_end, double step_work)
+{
+    const double d = fabs((g_end - g_start) - step_work);
+    werr = d > werr ? d : werr;
+    work += step_work;
 }
 
 __device__ __forceinline__ void ktrace_put(const PushArgs &a, int64_t kt_u, int64_t n, int8_t v)

@@ -88,8 +88,8 @@ struct pic_ctx {
     int32_t pred_every = 0;
     int64_t pred_calls = 0;
     uint64_t rebins = 0;
-    // dephasing diagnostic (allocated when first switched on)
-    double *r0 = nullptr, *rmax = nullptr;
+    // trajectory diagnostics (allocated when first switched on)
+    double *r0 = nullptr, *rmax = nullptr, *work = nullptr, *werr = nullptr;
     bool deph = false;
     // k trace
     int8_t *ktrace = nullptr;
@@ -156,7 +156,8 @@ void free_all(pic_ctx *c)
     c->graph = nullptr;
     void *ptrs[] = {c->x, c->px, c->py, c->pz, c->kold, c->status, c->perm, c->key,
                     c->d_runs, c->group_run, c->group_order, c->group_prio, c->wtab, c->cnt,
-                    c->r0, c->rmax, c->pred_w, c->pred_norm, c->pred_feat, c->pred_score};
+                    c->r0, c->rmax, c->work, c->werr, c->pred_w, c->pred_norm, c->pred_feat,
+                    c->pred_score};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (RunHost &r : c->runs) {
@@ -171,7 +172,7 @@ void free_all(pic_ctx *c)
     c->group_prio = nullptr;
     c->d_runs = nullptr;
     c->cnt = nullptr;
-    c->r0 = c->rmax = nullptr;
+    c->r0 = c->rmax = c->work = c->werr = nullptr;
     c->deph = false;
     c->pred_w = nullptr;
     c->pred_norm = c->pred_feat = c->pred_score = nullptr;
@@ -279,6 +280,8 @@ PushArgs push_args(pic_ctx *ctx, int64_t n0, int32_t S)
     a.ktrace = ctx->ktrace;
     a.r0 = ctx->deph ? ctx->r0 : nullptr;
     a.rmax = ctx->deph ? ctx->rmax : nullptr;
+    a.work = ctx->deph ? ctx->work : nullptr;
+    a.werr = ctx->deph ? ctx->werr : nullptr;
     a.cnt = ctx->cnt;
     a.kt_n0 = ctx->kt_n0;
     a.kt_first = ctx->kt_first;
@@ -290,36 +293,36 @@ PushArgs push_args(pic_ctx *ctx, int64_t n0, int32_t S)
     return a;
 }
 
-// DEPH: the dephasing diagnostic compiled in (only when it is switched on,
-// so the kernels without it keep their register budget)
-template <int P, int WPG, bool DEPH>
+// DIAG: the trajectory diagnostics compiled in (only when they are switched
+// on, so the kernels without them keep their register budget)
+template <int P, int WPG, bool DIAG>
 void launch_wave(const PushArgs &a, int precision, hipStream_t s)
 {
     const dim3 grid(unsigned((a.ngroups + WPG - 1) / WPG)), block(64 * WPG);
     if (precision == PIC_FP64)
-        push_wave_kernel<P, WPG, Arith::IEEE64, DEPH><<<grid, block, 0, s>>>(a);
+        push_wave_kernel<P, WPG, Arith::IEEE64, DIAG><<<grid, block, 0, s>>>(a);
     else if (precision == PIC_FP64_FAST)
-        push_fast_kernel<P, WPG, DEPH><<<grid, block, 0, s>>>(a);
+        push_fast_kernel<P, WPG, DIAG><<<grid, block, 0, s>>>(a);
     else
-        push_wave_fp32c_kernel<P, WPG, DEPH><<<grid, block, 0, s>>>(a);
+        push_wave_fp32c_kernel<P, WPG, DIAG><<<grid, block, 0, s>>>(a);
 }
 
-template <int P, bool DEPH>
+template <int P, bool DIAG>
 void launch_shape(const PushArgs &a, const pic_tune &t, int precision, int64_t slots, hipStream_t s)
 {
     if (t.binning == PIC_BIN_BALLOT) {
         const dim3 grid(unsigned(slots / t.tile));
         switch (t.tile) {
-        case 128: push_tile_kernel<P, 128, DEPH><<<grid, dim3(128), 0, s>>>(a); break;
-        case 512: push_tile_kernel<P, 512, DEPH><<<grid, dim3(512), 0, s>>>(a); break;
-        default: push_tile_kernel<P, 256, DEPH><<<grid, dim3(256), 0, s>>>(a); break;
+        case 128: push_tile_kernel<P, 128, DIAG><<<grid, dim3(128), 0, s>>>(a); break;
+        case 512: push_tile_kernel<P, 512, DIAG><<<grid, dim3(512), 0, s>>>(a); break;
+        default: push_tile_kernel<P, 256, DIAG><<<grid, dim3(256), 0, s>>>(a); break;
         }
         return;
     }
     switch (t.waves_per_group) {
-    case 2: launch_wave<P, 2, DEPH>(a, precision, s); break;
-    case 4: launch_wave<P, 4, DEPH>(a, precision, s); break;
-    default: launch_wave<P, 1, DEPH>(a, precision, s); break;
+    case 2: launch_wave<P, 2, DIAG>(a, precision, s); break;
+    case 4: launch_wave<P, 4, DIAG>(a, precision, s); break;
+    default: launch_wave<P, 1, DIAG>(a, precision, s); break;
     }
 }
 
@@ -644,9 +647,9 @@ pic_status load_particles(pic_ctx *ctx, pic_mem mem, const double *x, const doub
                            ctx->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     }
-    if (e == hipSuccess && ctx->deph) {          // new particles: the diagnostic restarts
-        dephasing_init_kernel<<<grid_for(ctx->slots, 256, 8192), 256, 0, ctx->stream>>>(
-            ctx->slots, ctx->px, ctx->py, ctx->pz, ctx->r0, ctx->rmax);
+    if (e == hipSuccess && ctx->deph) {          // new particles: the diagnostics restart
+        diag_init_kernel<<<grid_for(ctx->slots, 256, 8192), 256, 0, ctx->stream>>>(
+            ctx->slots, ctx->px, ctx->py, ctx->pz, ctx->r0, ctx->rmax, ctx->work, ctx->werr);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
@@ -1026,7 +1029,7 @@ pic_status pic_predictor_set(pic_ctx *ctx, const uint16_t *w_bf16, const float *
     return PIC_OK;
 }
 
-pic_status pic_dephasing_track(pic_ctx *ctx, int32_t on)
+pic_status pic_diag_track(pic_ctx *ctx, int32_t on)
 {
     CTX_CHECK(ctx);
     if (on != 0 && on != 1) return fail(ctx, PIC_E_ARG, "on must be 0 or 1");
@@ -1035,52 +1038,67 @@ pic_status pic_dephasing_track(pic_ctx *ctx, int32_t on)
         return PIC_OK;
     }
     const size_t n = size_t(ctx->slots);
-    pic_status st;
     if (!ctx->r0) {
-        if ((st = dev_alloc(ctx, &ctx->r0, n))) return st;
-        if ((st = dev_alloc(ctx, &ctx->rmax, n))) {
-            (void)hipFree(ctx->r0);
-            ctx->r0 = nullptr;
+        pic_status st;
+        if ((st = dev_alloc(ctx, &ctx->r0, n)) || (st = dev_alloc(ctx, &ctx->rmax, n)) ||
+            (st = dev_alloc(ctx, &ctx->work, n)) || (st = dev_alloc(ctx, &ctx->werr, n))) {
+            double *ps[4] = {ctx->r0, ctx->rmax, ctx->work, ctx->werr};
+            for (double *q : ps)
+                if (q) (void)hipFree(q);
+            ctx->r0 = ctx->rmax = ctx->work = ctx->werr = nullptr;
             return st;
         }
     }
-    dephasing_init_kernel<<<grid_for(ctx->slots, 256, 8192), 256, 0, ctx->stream>>>(
-        ctx->slots, ctx->px, ctx->py, ctx->pz, ctx->r0, ctx->rmax);
+    diag_init_kernel<<<grid_for(ctx->slots, 256, 8192), 256, 0, ctx->stream>>>(
+        ctx->slots, ctx->px, ctx->py, ctx->pz, ctx->r0, ctx->rmax, ctx->work, ctx->werr);
     LAUNCH_CHECK(ctx);
     ctx->deph = true;
     return PIC_OK;
 }
 
-pic_status pic_dephasing_read(pic_ctx *ctx, pic_mem mem, double *R0, double *rmax)
+namespace {
+// Two diagnostic arrays out in caller order.
+pic_status diag_out(pic_ctx *ctx, pic_mem mem, const double *a, const double *b, double *oa,
+                    double *ob)
 {
     CTX_CHECK(ctx);
     if (mem != PIC_MEM_HOST && mem != PIC_MEM_DEVICE) return fail(ctx, PIC_E_ARG, "bad pic_mem");
-    if (!ctx->r0) return fail(ctx, PIC_E_STATE, "the dephasing diagnostic was never switched on");
+    if (!ctx->r0) return fail(ctx, PIC_E_STATE, "the diagnostics were never switched on");
     const size_t n = size_t(ctx->np);
-    if (n == 0 || (!R0 && !rmax)) return PIC_OK;
+    if (n == 0 || (!oa && !ob)) return PIC_OK;
     const int grid = grid_for(ctx->slots, 256, 8192);
     if (mem == PIC_MEM_DEVICE) {
-        dephasing_read_kernel<<<grid, 256, 0, ctx->stream>>>(ctx->perm, ctx->slots, ctx->r0,
-                                                             ctx->rmax, R0, rmax);
+        slots_to_caller_kernel<<<grid, 256, 0, ctx->stream>>>(ctx->perm, ctx->slots, a, b, oa, ob);
         LAUNCH_CHECK(ctx);
         return PIC_OK;
     }
     double *d = nullptr;
     pic_status st = dev_alloc(ctx, &d, 2 * n);
     if (st) return st;
-    dephasing_read_kernel<<<grid, 256, 0, ctx->stream>>>(ctx->perm, ctx->slots, ctx->r0, ctx->rmax,
-                                                         d, d + n);
+    slots_to_caller_kernel<<<grid, 256, 0, ctx->stream>>>(ctx->perm, ctx->slots, a, b, d, d + n);
     hipError_t e = hipGetLastError();
-    if (e == hipSuccess && R0)
-        e = hipMemcpyAsync(R0, d, n * 8, hipMemcpyDeviceToHost, ctx->stream);
-    if (e == hipSuccess && rmax)
-        e = hipMemcpyAsync(rmax, d + n, n * 8, hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess && oa) e = hipMemcpyAsync(oa, d, n * 8, hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess && ob)
+        e = hipMemcpyAsync(ob, d + n, n * 8, hipMemcpyDeviceToHost, ctx->stream);
     const hipError_t e2 = hipStreamSynchronize(ctx->stream);
     (void)hipFree(d);
     if (e != hipSuccess || e2 != hipSuccess)
-        return fail(ctx, PIC_E_DEVICE, "dephasing read: %s",
+        return fail(ctx, PIC_E_DEVICE, "diagnostics read: %s",
                     hipGetErrorString(e != hipSuccess ? e : e2));
     return PIC_OK;
+}
+}  // namespace
+
+pic_status pic_dephasing_read(pic_ctx *ctx, pic_mem mem, double *R0, double *rmax)
+{
+    if (!ctx) return PIC_E_ARG;
+    return diag_out(ctx, mem, ctx->r0, ctx->rmax, R0, rmax);
+}
+
+pic_status pic_energy_read(pic_ctx *ctx, pic_mem mem, double *work, double *err_max)
+{
+    if (!ctx) return PIC_E_ARG;
+    return diag_out(ctx, mem, ctx->work, ctx->werr, work, err_max);
 }
 
 pic_status pic_tune_set(pic_ctx *ctx, const pic_tune *t)
@@ -1400,20 +1418,18 @@ pic_status pic_prebin(pic_ctx *ctx, const float *score, int32_t nbuckets, float 
         if (e == hipSuccess)
             e = hipMemcpyAsync(ctx->kold, nk, n, hipMemcpyDeviceToDevice, ctx->stream);
         if (e == hipSuccess && ctx->r0) {
-            // the dephasing arrays follow their particles (nsoa is free again;
+            // the diagnostics follow their particles (nsoa is free again;
             // ctx->perm still holds the old slot map)
-            e = hipMemcpyAsync(nsoa, ctx->r0, n * 8, hipMemcpyDeviceToDevice, ctx->stream);
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(nsoa + n, ctx->rmax, n * 8, hipMemcpyDeviceToDevice, ctx->stream);
-            if (e == hipSuccess) {
+            double *d4[4] = {ctx->r0, ctx->rmax, ctx->work, ctx->werr};
+            for (int a = 0; a < 4 && e == hipSuccess; ++a)
+                e = hipMemcpyAsync(nsoa + a * n, d4[a], n * 8, hipMemcpyDeviceToDevice, ctx->stream);
+            for (int a = 0; a < 4 && e == hipSuccess; a += 2) {
                 permute_pair_kernel<<<grid_for(slots, 256, 8192), 256, 0, ctx->stream>>>(
-                    dest, slots, ctx->perm, ctx->r0, ctx->rmax, nsoa, nsoa + n);
+                    dest, slots, ctx->perm, d4[a], d4[a + 1], nsoa + a * n, nsoa + (a + 1) * n);
                 e = hipGetLastError();
             }
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(ctx->r0, nsoa, n * 8, hipMemcpyDeviceToDevice, ctx->stream);
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(ctx->rmax, nsoa + n, n * 8, hipMemcpyDeviceToDevice, ctx->stream);
+            for (int a = 0; a < 4 && e == hipSuccess; ++a)
+                e = hipMemcpyAsync(d4[a], nsoa + a * n, n * 8, hipMemcpyDeviceToDevice, ctx->stream);
         }
         if (e == hipSuccess)
             e = hipMemcpyAsync(ctx->perm, nperm, n * 4, hipMemcpyDeviceToDevice, ctx->stream);

@@ -121,7 +121,7 @@ __device__ __forceinline__ double comb_lds(const double *p, int field, const W &
     return v;
 }
 
-template <int P, int WPG, bool DEPH = false>
+template <int P, int WPG, bool DIAG = false>
 __global__ void __launch_bounds__(64 * WPG) push_fast_kernel(PushArgs a)
 {
     constexpr int ROWS = 2 * (P + 1);                 // row 2j: E of level j, 2j+1: B
@@ -181,11 +181,13 @@ __global__ void __launch_bounds__(64 * WPG) push_fast_kernel(PushArgs a)
     }
     bool moved = false;
     const bool tracing = a.ktrace != nullptr;
-    constexpr bool deph = DEPH;   // dephasing diagnostic compiled in
-    double r0v = 1.0, rmx = 0.0;
+    constexpr bool deph = DIAG;   // trajectory diagnostics compiled in
+    double r0v = 1.0, rmx = 0.0, wacc = 0.0, wem = 0.0;
     if (deph && mine) {
         r0v = a.r0[s];
         rmx = a.rmax[s];
+        wacc = a.work[s];
+        wem = a.werr[s];
     }
     // launch steps whose k is recorded: [kt_lo, kt_hi)
     int kt_lo = 0, kt_hi = 0;
@@ -320,9 +322,11 @@ __global__ void __launch_bounds__(64 * WPG) push_fast_kernel(PushArgs a)
         }
 
         bool done = false;
+        double gst = 1.0, swork = 0.0;     // diagnostics: gamma at the step start, step work
         if (live) {
             moved = true;
             kold = k;
+            if (deph) gst = gamma_of(px, py, pz);
             // dt*_new / dt and dt*_old / dt (negative: cold start, p lags
             // x by half of this step's sub-step)
             const double fnew = ldexp(1.0, -2 * k);
@@ -344,9 +348,12 @@ __global__ void __launch_bounds__(64 * WPG) push_fast_kernel(PushArgs a)
                     e0 = ringE[lv.off[P] + iE];
                     e1 = ringE[lv.off[P] + iE + 1];
                 }
-                boris_fma(c1, tent_fma(uE - flE, e0, e1), Bd, onepz, px, py);
+                const double Ek = tent_fma(uE - flE, e0, e1);
+                const double vb = deph ? py * ig : 0.0;
+                boris_fma(c1, Ek, Bd, onepz, px, py);
                 ig = rsq_1nr(fma(px, px, fma(py, py, onepz)));
                 x = fma(rdx, px * ig, x);
+                if (deph) swork = sub_step_work(c1, Ek, vb, py * ig);
                 done = true;
             } else {
                 set_prio(prio + 2);
@@ -378,10 +385,12 @@ __global__ void __launch_bounds__(64 * WPG) push_fast_kernel(PushArgs a)
                         e0 = comb_fma<P>(ringE, lv.off, ie, Wk);
                         e1 = comb_fma<P>(ringE, lv.off, ie + 1, Wk);
                     }
-                    boris_fma(j == 1 ? c1 : cn, tent_fma(uE - fe, e0, e1),
-                              tent_fma(x - fb, bb0, bb1), onepz, px, py);
+                    const double Es = tent_fma(uE - fe, e0, e1);
+                    const double vb = deph ? py * ig : 0.0;
+                    boris_fma(j == 1 ? c1 : cn, Es, tent_fma(x - fb, bb0, bb1), onepz, px, py);
                     ig = rsq_1nr(fma(px, px, fma(py, py, onepz)));
                     x = fma(rdx, px * ig, x);
+                    if (deph) swork += sub_step_work(j == 1 ? c1 : cn, Es, vb, py * ig);
                 }
                 set_prio(prio);
                 if (!done) status = PIC_PARTICLE_LOST;
@@ -389,7 +398,10 @@ __global__ void __launch_bounds__(64 * WPG) push_fast_kernel(PushArgs a)
         }
         cnt.steps_done(done, k);
         cnt.lost += __popcll(wballot(live & !done));
-        if (deph && done) dephasing_update(rmx, r0v, px, py, pz);
+        if (deph && done) {
+            dephasing_update(rmx, r0v, px, py, pz);
+            energy_close(wacc, wem, gst, gamma_of(px, py, pz), swork);
+        }
 
         // hand the step-ahead window to LDS for the next step
         if (pf_next) {
@@ -415,7 +427,11 @@ __global__ void __launch_bounds__(64 * WPG) push_fast_kernel(PushArgs a)
         }
         a.kold[s] = int8_t(kold);
         a.status[s] = status;
-        if (deph) a.rmax[s] = rmx;
+        if (deph) {
+            a.rmax[s] = rmx;
+            a.work[s] = wacc;
+            a.werr[s] = wem;
+        }
     }
     cnt.flush(a.cnt + (int64_t(run) * NSLOT + pos % NSLOT) * NCNT, lane);
 }

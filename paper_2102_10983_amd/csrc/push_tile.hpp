@@ -25,7 +25,7 @@ namespace picsub {
 
 constexpr int WMAX = 256;   // staged nodes per field level
 
-template <int P, int TILE, bool DEPH = false>
+template <int P, int TILE, bool DIAG = false>
 __global__ void __launch_bounds__(TILE) push_tile_kernel(PushArgs a)
 {
     constexpr int STRIDE = 2 * (P + 1);
@@ -35,6 +35,7 @@ __global__ void __launch_bounds__(TILE) push_tile_kernel(PushArgs a)
     __shared__ double sBh[WMAX];
     __shared__ double sx[TILE], spx[TILE], spy[TILE], spz[TILE];
     __shared__ uint8_t sst[TILE];
+    __shared__ double swk[DIAG ? TILE : 1];    // work of a sub-cycled step (diagnostics)
     __shared__ uint16_t sq[PIC_K_MAX_LIMIT + 1][TILE];
     __shared__ int sqn[PIC_K_MAX_LIMIT + 1];
     __shared__ int slo[2], shi[2];   // window bounds, double-buffered by step parity
@@ -64,11 +65,13 @@ __global__ void __launch_bounds__(TILE) push_tile_kernel(PushArgs a)
     int kold = 0;
     uint8_t status = PIC_PARTICLE_LOST;
     int64_t kt_u = -1;
-    constexpr bool deph = DEPH;   // dephasing diagnostic compiled in
-    double r0v = 1.0, rmx = 0.0;
+    constexpr bool deph = DIAG;   // trajectory diagnostics compiled in
+    double r0v = 1.0, rmx = 0.0, wacc = 0.0, wem = 0.0;
     if (deph && mine) {
         r0v = a.r0[i];
         rmx = a.rmax[i];
+        wacc = a.work[i];
+        wem = a.werr[i];
     }
     if (mine) {
         x = a.x[i];
@@ -142,6 +145,7 @@ __global__ void __launch_bounds__(TILE) push_tile_kernel(PushArgs a)
         // -- 2. decision, k = 0 steps in place
         bool heavy = false;
         int k = 0;
+        double gst = 1.0;                  // diagnostics: gamma at the step start
         if (live) {
             const double flB = floor(xi);
             const int iB = int(flB);
@@ -157,6 +161,7 @@ __global__ void __launch_bounds__(TILE) push_tile_kernel(PushArgs a)
             const double Bd = (1.0 - wB) * f0 + wB * f1;
             const double g0 = sqrt(1.0 + ((px * px + py * py) + pz * pz));
             const double psi0 = fabs(c0 * Bd) / g0;
+            gst = g0;
             double lim = R.psi_max;
             while (psi0 > lim && k < R.kmax) {
                 ++k;
@@ -181,11 +186,16 @@ __global__ void __launch_bounds__(TILE) push_tile_kernel(PushArgs a)
                 }
                 const double E = (1.0 - wE) * e0 + wE * e1;
                 const double dto = ldexp(R.dt, -2 * ko);
+                const double vb = deph ? py / g0 : 0.0;
                 boris(R.qm, 0.5 * (dto + R.dt), E, Bd, px, py, pz);
                 const double g2 = sqrt(1.0 + ((px * px + py * py) + pz * pz));
                 x = x + R.dt * (px / g2);
                 cnt.step_done(0);
-                if (deph) dephasing_update(rmx, r0v, px, py, pz);
+                if (deph) {
+                    dephasing_update(rmx, r0v, px, py, pz);
+                    energy_close(wacc, wem, g0, gamma_of(px, py, pz),
+                                 sub_step_work((0.5 * R.qm) * (0.5 * (dto + R.dt)), E, vb, py / g2));
+                }
             } else {
                 heavy = true;
                 sx[t] = x;
@@ -230,6 +240,7 @@ __global__ void __launch_bounds__(TILE) push_tile_kernel(PushArgs a)
                 const int nsub = 1 << (2 * kk);
                 const double *Wk = a.wtab + wtab_offset(kk) * STRIDE;
                 uint8_t hst = PIC_PARTICLE_LIVE;
+                double hsw = 0.0, hg = deph ? gamma_of(hpx, hpy, hpz) : 1.0;
                 for (int j = 1; j <= nsub; ++j, Wk += STRIDE) {
                     const double hxi = (hx - R.x_origin) / R.dx;
                     if (!(hxi >= 0.5 && hxi < ncm1)) {
@@ -258,10 +269,16 @@ __global__ void __launch_bounds__(TILE) push_tile_kernel(PushArgs a)
                     const double B = (1.0 - wB) * b0 + wB * b1;
                     const double E = (1.0 - wE) * e0 + wE * e1;
                     const double dtp = j == 1 ? 0.5 * (dt_old + dt_new) : dt_new;
+                    const double vb = deph ? hpy / hg : 0.0;
                     boris(R.qm, dtp, E, B, hpx, hpy, hpz);
                     const double g2 = sqrt(1.0 + ((hpx * hpx + hpy * hpy) + hpz * hpz));
                     hx = hx + dt_new * (hpx / g2);
+                    if (deph) {
+                        hsw += sub_step_work((0.5 * R.qm) * dtp, E, vb, hpy / g2);
+                        hg = g2;
+                    }
                 }
+                if (deph) swk[who] = hsw;
                 sx[who] = hx;
                 spx[who] = hpx;
                 spy[who] = hpy;
@@ -276,7 +293,10 @@ __global__ void __launch_bounds__(TILE) push_tile_kernel(PushArgs a)
                 pz = spz[t];
                 if (sst[t] == 0xFF) {
                     cnt.step_done(k);
-                    if (deph) dephasing_update(rmx, r0v, px, py, pz);
+                    if (deph) {
+                        dephasing_update(rmx, r0v, px, py, pz);
+                        energy_close(wacc, wem, gst, gamma_of(px, py, pz), swk[t]);
+                    }
                 } else {
                     status = PIC_PARTICLE_LOST;
                     ++cnt.lost;
@@ -292,7 +312,11 @@ __global__ void __launch_bounds__(TILE) push_tile_kernel(PushArgs a)
         a.pz[i] = pz;
         a.kold[i] = int8_t(kold);
         a.status[i] = status;
-        if (deph) a.rmax[i] = rmx;
+        if (deph) {
+            a.rmax[i] = rmx;
+            a.work[i] = wacc;
+            a.werr[i] = wem;
+        }
     }
     flush_wave(cnt, a.cnt + (int64_t(run) * NSLOT + blockIdx.x % NSLOT) * NCNT, lane);
 }

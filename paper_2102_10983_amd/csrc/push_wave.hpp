@@ -22,7 +22,7 @@ namespace picsub {
 
 enum class Arith { IEEE64, FAST64 };
 
-template <int P, int WPG, Arith AR, bool DEPH = false>
+template <int P, int WPG, Arith AR, bool DIAG = false>
 __global__ void __launch_bounds__(64 * WPG) push_wave_kernel(PushArgs a)
 {
     constexpr int STRIDE = 2 * (P + 1);
@@ -69,11 +69,13 @@ __global__ void __launch_bounds__(64 * WPG) push_wave_kernel(PushArgs a)
         }
     }
     bool moved = false;
-    constexpr bool deph = DEPH;   // dephasing diagnostic compiled in
-    double r0v = 1.0, rmx = 0.0;
+    constexpr bool deph = DIAG;   // trajectory diagnostics compiled in
+    double r0v = 1.0, rmx = 0.0, wacc = 0.0, wem = 0.0;
     if (deph && mine) {
         r0v = a.r0[s];
         rmx = a.rmax[s];
+        wacc = a.work[s];
+        wem = a.werr[s];
     }
 
     const int S_run = run_steps(a, R, n0);
@@ -95,6 +97,7 @@ __global__ void __launch_bounds__(64 * WPG) push_wave_kernel(PushArgs a)
         int k = 0, cell = 0;
         double Bd = 0.0;
         bool clamped = false;
+        double gst = 1.0, sw = 0.0;        // diagnostics: gamma at the step start, step work
         if (live) {
             const double flB = floor(xi);
             cell = int(flB);
@@ -105,9 +108,11 @@ __global__ void __launch_bounds__(64 * WPG) push_wave_kernel(PushArgs a)
             double psi0;
             if (FAST) {
                 psi0 = fabs(c0 * Bd) * ig;
+                if (deph) gst = gamma_of(px, py, pz);
             } else {
                 const double g0 = sqrt(1.0 + ((px * px + py * py) + pz * pz));
                 psi0 = fabs(c0 * Bd) / g0;
+                gst = g0;
             }
             double lim = R.psi_max;
             while (psi0 > lim && k < R.kmax) {
@@ -155,14 +160,17 @@ __global__ void __launch_bounds__(64 * WPG) push_wave_kernel(PushArgs a)
             const double e1 = R.ringE[lv.off[P] + iE + 1];
             const double E = (1.0 - wE) * e0 + wE * e1;
             const double dtp = 0.5 * (dt_old + dt_new);
+            const double vb = deph ? py / gst : 0.0;
             if (FAST) {
                 boris_fast(R.qm, dtp, E, Bd, px, py, pz);
                 ig = rsq_nr(1.0 + ((px * px + py * py) + pz * pz));
                 x = x + rdx * (px * ig);
+                if (deph) sw = sub_step_work((0.5 * R.qm) * dtp, E, vb, py * ig);
             } else {
                 boris(R.qm, dtp, E, Bd, px, py, pz);
                 const double g2 = sqrt(1.0 + ((px * px + py * py) + pz * pz));
                 x = x + dt_new * (px / g2);
+                if (deph) sw = sub_step_work((0.5 * R.qm) * dtp, E, vb, py / g2);
             }
             done = true;
         } else {
@@ -173,6 +181,7 @@ __global__ void __launch_bounds__(64 * WPG) push_wave_kernel(PushArgs a)
             const int nsub = 1 << (2 * k);
             const double *Wk = a.wtab + wtab_offset(k) * STRIDE;
             done = true;
+            double gcur = gst;                 // gamma of the momentum before the sub-step
             for (int j = 1; j <= nsub; ++j, Wk += STRIDE) {
                 if (j > 1) {
                     xi = FAST ? x : (x - R.x_origin) / R.dx;
@@ -203,14 +212,23 @@ __global__ void __launch_bounds__(64 * WPG) push_wave_kernel(PushArgs a)
                 const double B = (1.0 - wb) * bb0 + wb * bb1;
                 const double E = (1.0 - we) * e0 + we * e1;
                 const double dtp = j == 1 ? 0.5 * (dt_old + dt_new) : dt_new;
+                const double vb = deph ? py / gcur : 0.0;
                 if (FAST) {
                     boris_fast(R.qm, dtp, E, B, px, py, pz);
                     ig = rsq_nr(1.0 + ((px * px + py * py) + pz * pz));
                     x = x + rdx * (px * ig);
+                    if (deph) {
+                        gcur = gamma_of(px, py, pz);
+                        sw += sub_step_work((0.5 * R.qm) * dtp, E, vb, py / gcur);
+                    }
                 } else {
                     boris(R.qm, dtp, E, B, px, py, pz);
                     const double g2 = sqrt(1.0 + ((px * px + py * py) + pz * pz));
                     x = x + dt_new * (px / g2);
+                    if (deph) {
+                        sw += sub_step_work((0.5 * R.qm) * dtp, E, vb, py / g2);
+                        gcur = g2;
+                    }
                 }
             }
             set_prio(prio);
@@ -219,7 +237,10 @@ __global__ void __launch_bounds__(64 * WPG) push_wave_kernel(PushArgs a)
         }
         cnt.steps_done(done, k);
         cnt.lost += __popcll(__ballot(live && !done));
-        if (deph && done) dephasing_update(rmx, r0v, px, py, pz);
+        if (deph && done) {
+            dephasing_update(rmx, r0v, px, py, pz);
+            energy_close(wacc, wem, gst, gamma_of(px, py, pz), sw);
+        }
     }
     if (mine) {
         if (moved) {
@@ -230,7 +251,11 @@ __global__ void __launch_bounds__(64 * WPG) push_wave_kernel(PushArgs a)
         }
         a.kold[s] = int8_t(kold);
         a.status[s] = status;
-        if (deph) a.rmax[s] = rmx;
+        if (deph) {
+            a.rmax[s] = rmx;
+            a.work[s] = wacc;
+            a.werr[s] = wem;
+        }
     }
     cnt.flush(a.cnt + (int64_t(run) * NSLOT + pos % NSLOT) * NCNT, lane);
 }
@@ -252,7 +277,7 @@ __global__ void __launch_bounds__(64 * WPG) push_wave_kernel(PushArgs a)
 // by gamma: this mode trades accuracy (a few 1e-5 at a0 ~ 10..150) for
 // arithmetic width.
 // ---------------------------------------------------------------------
-template <int P, int WPG, bool DEPH = false>
+template <int P, int WPG, bool DIAG = false>
 __global__ void __launch_bounds__(64 * WPG) push_wave_fp32c_kernel(PushArgs a)
 {
     constexpr int STRIDE = 2 * (P + 1);
@@ -291,11 +316,13 @@ __global__ void __launch_bounds__(64 * WPG) push_wave_fp32c_kernel(PushArgs a)
     int kold = 0;
     uint8_t status = PIC_PARTICLE_LOST;
     int64_t kt_u = -1;
-    constexpr bool deph = DEPH;   // dephasing diagnostic compiled in
-    double r0v = 1.0, rmx = 0.0;
+    constexpr bool deph = DIAG;   // trajectory diagnostics compiled in
+    double r0v = 1.0, rmx = 0.0, wacc = 0.0, wem = 0.0;
     if (deph && mine) {
         r0v = a.r0[s];
         rmx = a.rmax[s];
+        wacc = a.work[s];
+        wem = a.werr[s];
     }
     if (mine) {
         const double xi = (a.x[s] - R.x_origin) / R.dx;
@@ -392,10 +419,14 @@ __global__ void __launch_bounds__(64 * WPG) push_wave_fp32c_kernel(PushArgs a)
             wave_lds_sync();
         }
         bool done = false;
+        double gst = 1.0, sw = 0.0;        // diagnostics: gamma at the step start, step work
         if (live) {
         moved = true;
         const int ko = kold < 0 ? k : kold;
         kold = k;
+        if (deph)
+            gst = gamma_of(double(pxh) + double(pxl), double(pyh) + double(pyl),
+                           double(pzh) + double(pzl));
         if (!heavy) {
             float e0, e1;
             if (use_lds) {
@@ -407,6 +438,7 @@ __global__ void __launch_bounds__(64 * WPG) push_wave_fp32c_kernel(PushArgs a)
             }
             const float E = (1.f - wE) * e0 + wE * e1;
             const float cf = float(0.5 * R.qm * (0.5 * (ldexp(R.dt, -2 * ko) + R.dt)));
+            const double vb = deph ? (double(pyh) + double(pyl)) / gst : 0.0;
             const float h = cf * E;
             const float mx = pxh, my = pyh + h, mz = pzh;
             const float igf = __builtin_amdgcn_rsqf(1.f + ((mx * mx + my * my) + mz * mz));
@@ -416,6 +448,12 @@ __global__ void __launch_bounds__(64 * WPG) push_wave_fp32c_kernel(PushArgs a)
             const float ay = my - mx * t;
             comp_add(pxh, pxl, ay * sz);
             comp_add(pyh, pyl, (h + h) - ax * sz);
+            if (deph) {
+                const double pya = double(pyh) + double(pyl);
+                const double ga = gamma_of(double(pxh) + double(pxl), pya, double(pzh) + double(pzl));
+                sw = sub_step_work((0.5 * R.qm) * (0.5 * (ldexp(R.dt, -2 * ko) + R.dt)), double(E),
+                                   vb, pya / ga);
+            }
             const float q2 = (pyh * pyh + pzh * pzh);
             const float g2 = __builtin_amdgcn_sqrtf(1.f + (pxh * pxh + q2));
             const float omv = (1.f + q2) * __builtin_amdgcn_rcpf(g2 * (g2 + fabsf(pxh)));  // 1 - |v|
@@ -447,6 +485,7 @@ __global__ void __launch_bounds__(64 * WPG) push_wave_fp32c_kernel(PushArgs a)
             for (int j = 0; j <= P; ++j) vo[j] = j * WWIN - lo;
             const double ncm1 = double(R.ncells - 1);
             done = true;
+            double gcur = gst;
             for (int j = 1; j <= nsub; ++j, Wk += STRIDE) {
                 if (!(xi >= 0.5 && xi < ncm1)) {
                     done = false;
@@ -474,9 +513,14 @@ __global__ void __launch_bounds__(64 * WPG) push_wave_fp32c_kernel(PushArgs a)
                 const double B = (1.0 - wb) * bb0 + wb * bb1;
                 const double E = (1.0 - we) * ee0 + we * ee1;
                 const double dtp = j == 1 ? 0.5 * (dt_old + dt_new) : dt_new;
+                const double vb = deph ? py / gcur : 0.0;
                 boris(R.qm, dtp, E, B, px, py, pz);
                 const double g2 = sqrt(1.0 + ((px * px + py * py) + pz * pz));
                 xi = xi + rdx * (px / g2);
+                if (deph) {
+                    sw += sub_step_work((0.5 * R.qm) * dtp, E, vb, py / g2);
+                    gcur = g2;
+                }
             }
             set_prio(prio);
             if (!done) status = PIC_PARTICLE_LOST;
@@ -490,12 +534,19 @@ __global__ void __launch_bounds__(64 * WPG) push_wave_fp32c_kernel(PushArgs a)
         }
         cnt.steps_done(done, k);
         cnt.lost += __popcll(__ballot(live && !done));
-        if (deph && done)
-            dephasing_update(rmx, r0v, double(pxh) + double(pxl), double(pyh) + double(pyl),
-                             double(pzh) + double(pzl));
+        if (deph && done) {
+            const double qx = double(pxh) + double(pxl), qy = double(pyh) + double(pyl);
+            const double qz = double(pzh) + double(pzl);
+            dephasing_update(rmx, r0v, qx, qy, qz);
+            energy_close(wacc, wem, gst, gamma_of(qx, qy, qz), sw);
+        }
     }
     if (mine) {
-        if (deph) a.rmax[s] = rmx;
+        if (deph) {
+            a.rmax[s] = rmx;
+            a.work[s] = wacc;
+            a.werr[s] = wem;
+        }
         if (moved) {
             const double xi = double(cell) + (double(fr) + double(frc));
             a.x[s] = R.x_origin + xi * R.dx;

@@ -269,33 +269,35 @@ __global__ void diag_kernel(const int32_t *__restrict__ perm, int64_t slots,
     }
 }
 
-// Dephasing diagnostic: R0 = gamma - p_x of the stored momentum of every
-// slot, running maximum reset to zero.
-__global__ void dephasing_init_kernel(int64_t slots, const double *__restrict__ px,
-                                      const double *__restrict__ py,
-                                      const double *__restrict__ pz, double *__restrict__ r0,
-                                      double *__restrict__ rmax)
+// Trajectory diagnostics: R0 = gamma - p_x of the stored momentum of every
+// slot; running maximum, work and largest step energy error reset to zero.
+__global__ void diag_init_kernel(int64_t slots, const double *__restrict__ px,
+                                 const double *__restrict__ py, const double *__restrict__ pz,
+                                 double *__restrict__ r0, double *__restrict__ rmax,
+                                 double *__restrict__ work, double *__restrict__ werr)
 {
     for (int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; s < slots;
          s += int64_t(gridDim.x) * blockDim.x) {
         const double a = px[s], b = py[s], c = pz[s];
         r0[s] = sqrt(1.0 + ((a * a + b * b) + c * c)) - a;
         rmax[s] = 0.0;
+        work[s] = 0.0;
+        werr[s] = 0.0;
     }
 }
 
-// R0 and the running maximum in caller order.
-__global__ void dephasing_read_kernel(const int32_t *__restrict__ perm, int64_t slots,
-                                      const double *__restrict__ r0,
-                                      const double *__restrict__ rmax, double *__restrict__ o_r0,
-                                      double *__restrict__ o_rmax)
+// Two per-slot arrays in caller order (either output may be null).
+__global__ void slots_to_caller_kernel(const int32_t *__restrict__ perm, int64_t slots,
+                                       const double *__restrict__ a,
+                                       const double *__restrict__ b, double *__restrict__ oa,
+                                       double *__restrict__ ob)
 {
     for (int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; s < slots;
          s += int64_t(gridDim.x) * blockDim.x) {
         const int32_t u = perm[s];
         if (u < 0) continue;
-        if (o_r0) o_r0[u] = r0[s];
-        if (o_rmax) o_rmax[u] = rmax[s];
+        if (oa) oa[u] = a[s];
+        if (ob) ob[u] = b[s];
     }
 }
 

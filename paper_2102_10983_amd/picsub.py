@@ -33,7 +33,8 @@ EXPORTS = ("pic_create", "pic_destroy", "pic_last_error", "pic_particles_set",
            "pic_group_count", "pic_order_set", "pic_features", "pic_mlp_forward",
            "pic_mlp_grad", "pic_mlp_adam", "pic_prebin", "pic_state_export",
            "pic_state_import", "pic_fields_yee", "pic_fields_yee_r", "pic_fields_read",
-           "pic_fields_read_r", "pic_dephasing_track", "pic_dephasing_read",
+           "pic_fields_read_r", "pic_diag_track", "pic_dephasing_read",
+           "pic_energy_read",
            "pic_predictor_set")
 
 MLP_FEATURES = 8
@@ -131,7 +132,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "pic_fields_yee_r": ([vp, i32, i64, i32, vp, i64, i64, i64], C.c_int),
         "pic_fields_read": ([vp, i64, C.c_int, vp, vp], C.c_int),
         "pic_fields_read_r": ([vp, i32, i64, C.c_int, vp, vp], C.c_int),
-        "pic_dephasing_track": ([vp, i32], C.c_int),
+        "pic_diag_track": ([vp, i32], C.c_int),
+        "pic_energy_read": ([vp, C.c_int, vp, vp], C.c_int),
         "pic_predictor_set": ([vp, vp, vp, vp, C.c_float, i32], C.c_int),
         "pic_dephasing_read": ([vp, C.c_int, vp, vp], C.c_int),
     }
@@ -321,9 +323,10 @@ class Pusher:
         self._check(self._lib.pic_predictor_set(self._ctx, w.ctypes.data, nm.ctypes.data,
                                                 a0.ctypes.data, float(width), int(every)))
 
-    def dephasing_track(self, on: bool = True):
-        """Start (restart) or stop the running max of |R - R0| / R0, R = gamma - p_x."""
-        self._check(self._lib.pic_dephasing_track(self._ctx, 1 if on else 0))
+    def diag_track(self, on: bool = True):
+        """Start (restart) or stop the trajectory diagnostics: running max of
+        |R - R0| / R0 (R = gamma - p_x) and the work / energy accounting."""
+        self._check(self._lib.pic_diag_track(self._ctx, 1 if on else 0))
 
     def dephasing_read(self):
         """(R0, running max of |R - R0| / R0) per particle, host arrays."""
@@ -332,6 +335,14 @@ class Pusher:
         self._check(self._lib.pic_dephasing_read(self._ctx, MEM_HOST, R0.ctypes.data,
                                                  rm.ctypes.data))
         return R0, rm
+
+    def energy_read(self):
+        """(work of E since the start, largest single-step |d gamma - work|)
+        per particle, host arrays."""
+        w = np.empty(self.num)
+        e = np.empty(self.num)
+        self._check(self._lib.pic_energy_read(self._ctx, MEM_HOST, w.ctypes.data, e.ctypes.data))
+        return w, e
 
     def push(self, n: int, S: int = 1):
         self._check(self._lib.pic_push_subcycled(self._ctx, n, S))

@@ -1,13 +1,15 @@
-"""GPU tests of the dephasing diagnostic (Sec. V, Eq. (R error)): the
-running maximum of |R - R0| / R0, R = gamma - p_x, kept by every push
-kernel when switched on.
+"""GPU tests of the trajectory diagnostics kept by every push kernel when
+switched on: the running maximum of |R - R0| / R0, R = gamma - p_x (Sec. V,
+Eq. (R error)), and the energy accounting of App. B (work of E per
+sub-step, largest single-step |d gamma - work|).
 
 * PIC_FP64 (wavefront and ballot kernels, one launch and chunks of 16):
-  R0 and the maximum bit-identical to the FP64 oracle stepping one step at
-  a time (oracle.push_diagnostics).
-* PIC_FP64_FAST: within the bound the 1e-5 bar on p implies,
-  |d(R / R0)| <= 2 * 1e-5 * max|p| / R0, on electrons whose k sequence
-  matches the oracle's (others are replayed with the device's k).
+  all four arrays bit-identical to the FP64 oracle stepping one step at a
+  time (oracle.push_diagnostics).
+* PIC_FP64_FAST: within the bounds the 1e-5 bar on p implies,
+  |d(R / R0)| <= 2e-5 max|p| / R0 and |d work|, |d err| <= 4e-5 max|p|, on
+  electrons whose k sequence matches the oracle's (others are replayed
+  with the device's k).
 * Switching off freezes the values; re-binning carries them with the
   particles; loading particles restarts them.
 """
@@ -39,12 +41,14 @@ def _gpu(torch, wl, S, precision, binning, fields="lattice"):
     from paper_2102_10983_amd import runner
     run = runner.DeviceRun(wl, S=S, precision=precision, binning=binning, fields=fields)
     run.reset()
-    run.pusher.dephasing_track(True)
+    run.pusher.diag_track(True)
     buf = torch.full((wl.steps, wl.num), -2, dtype=torch.int8, device="cuda")
     run.pusher.ktrace_set(buf, 0, 0)
     run.advance(wl.steps)
     R0, rmax = run.pusher.dephasing_read()
+    work, werr = run.pusher.energy_read()
     d = run.diag()
+    d["work"], d["werr"] = work, werr
     kt = buf.cpu().numpy()
     run.close()
     return R0, rmax, d, kt
@@ -56,8 +60,9 @@ def _oracle(wl, fields=None, forced_k=None, idx=None):
     idx = np.arange(wl.num) if idx is None else idx
     st = O.State(wl.x0[idx], wl.p0[0][idx], wl.p0[1][idx], wl.p0[2][idx])
     fs = oracle_fields(wl) if fields is None else fields
-    R0, rmax, _, _, kt = O.push_diagnostics(oracle_params(wl), fs, st, 0, wl.steps,
-                                             forced_k=forced_k)
+    R0, rmax, work, werr, kt = O.push_diagnostics(oracle_params(wl), fs, st, 0, wl.steps,
+                                                   forced_k=forced_k)
+    st.work, st.werr = work, werr
     return R0, rmax, kt, st
 
 
@@ -71,8 +76,9 @@ def test_fp64_bitwise(torch_gpu, S, binning):
     assert np.array_equal(R0, oR0)
     assert np.array_equal(rmax, ormax)
     assert np.array_equal(d["px"], st.px)
-    _say("max eps_dephasing", float(rmax.max()))
-    assert rmax.max() > 0
+    assert np.array_equal(d["work"], st.work) and np.array_equal(d["werr"], st.werr)
+    _say("max eps_dephasing", float(rmax.max()), "max step energy error", float(d["werr"].max()))
+    assert rmax.max() > 0 and d["werr"].max() > 0 and d["work"].max() > 1.0
 
 
 def test_fp64_bitwise_with_losses_and_standard_pic(torch_gpu):
@@ -85,6 +91,7 @@ def test_fp64_bitwise_with_losses_and_standard_pic(torch_gpu):
     assert d["counters"]["lost"] > 0
     assert np.array_equal(kt, okt)
     assert np.array_equal(R0, oR0) and np.array_equal(rmax, ormax)
+    assert np.array_equal(d["work"], st.work) and np.array_equal(d["werr"], st.werr)
     assert np.ptp(R0) > 0.01
 
 
@@ -94,17 +101,23 @@ def test_fp64fast_within_the_implied_bound(torch_gpu, a0, theta):
     R0, rmax, d, kt = _gpu(torch_gpu, wl, wl.steps, "fp64fast", "none")
     oR0, ormax, okt, st = _oracle(wl)
     same = np.all(kt == okt, axis=0)
+    owork, owerr = st.work.copy(), st.werr.copy()
     if not same.all():
         idx = np.nonzero(~same)[0]
-        _, fr, _, _ = _oracle(wl, forced_k=np.ascontiguousarray(kt[:, idx]), idx=idx)
+        _, fr, _, fst = _oracle(wl, forced_k=np.ascontiguousarray(kt[:, idx]), idx=idx)
         ormax = ormax.copy()
         ormax[idx] = fr
+        owork[idx], owerr[idx] = fst.work, fst.werr
     pmax = a0 * a0 / 2 + a0 + 1.0               # bound on |p| along a plane-wave orbit
     bound = 2 * 1e-5 * pmax / oR0
     err = np.abs(rmax - ormax)
+    ew = np.abs(d["work"] - owork)
+    ee = np.abs(d["werr"] - owerr)
     _say(f"a0={a0}: flips {int((~same).sum())}, max |d rmax| {err.max():.3e}, "
-         f"largest allowed {bound.min():.3e}")
+         f"largest allowed {bound.min():.3e}; max |d work| {ew.max():.3e}, "
+         f"max |d err| {ee.max():.3e}, allowed {4e-5 * pmax:.3e}")
     assert np.all(err <= bound)
+    assert np.all(ew <= 4e-5 * pmax) and np.all(ee <= 4e-5 * pmax)
     assert np.allclose(R0, oR0, rtol=1e-12, atol=0)
 
 
@@ -117,7 +130,7 @@ def test_off_freezes_prebin_carries_load_restarts(torch_gpu):
     def run_once(rebin):
         run = runner.DeviceRun(wl, S=wl.steps, precision="fp64", binning="none")
         run.reset()
-        run.pusher.dephasing_track(True)
+        run.pusher.diag_track(True)
         run.advance(half)
         if rebin:      # a score that reverses positions moves every particle
             score = torch.from_numpy(-wl.x0.astype(np.float32)).cuda()
@@ -127,15 +140,18 @@ def test_off_freezes_prebin_carries_load_restarts(torch_gpu):
 
     ref = run_once(False)
     _, m_ref = ref.pusher.dephasing_read()
+    w_ref = ref.pusher.energy_read()
     ref.close()
     run = run_once(True)
     R0, m = run.pusher.dephasing_read()
     assert np.array_equal(m, m_ref) and np.all(R0 == 1.0) and m.max() > 0
-    run.pusher.dephasing_track(False)              # off: later steps change nothing
+    w = run.pusher.energy_read()
+    assert np.array_equal(w[0], w_ref[0]) and np.array_equal(w[1], w_ref[1])
+    run.pusher.diag_track(False)              # off: later steps change nothing
     run.advance(40)
     _, m_off = run.pusher.dephasing_read()
     assert np.array_equal(m_off, m)
-    run.pusher.dephasing_track(True)               # on again: restarts from the state now
+    run.pusher.diag_track(True)               # on again: restarts from the state now
     R0b, m0 = run.pusher.dephasing_read()
     assert np.all(m0 == 0.0) and not np.all(R0b == 1.0)
     run.advance(20)
@@ -143,4 +159,5 @@ def test_off_freezes_prebin_carries_load_restarts(torch_gpu):
     run.reset()                                    # loading particles restarts it
     R0c, mc = run.pusher.dephasing_read()
     assert np.all(mc == 0.0) and np.all(R0c == 1.0)
+    assert not run.pusher.energy_read()[0].any()
     run.close()
