@@ -45,8 +45,13 @@ class DeviceRun:
     def reset(self, k_old=None):
         """Load the initial state (device to device) and the first levels."""
         self.pusher.particles_set(self.x0, *self.p0, k_old)
-        first = self.order + (1 if self.fields == "yee" else 0)
-        self.pusher.fields_load_lattice(-self.order, first, self.table, self.M, self.coeffs)
+        # levels -hist .. -1 (the push needs -order; the predictor's features
+        # read -2 as well), and level 0 when the Yee solver makes the rest
+        extra = 1 if self.fields == "yee" else 0
+        hist = max(self.order, 2)
+        if hist + extra > self.pusher.ring_depth:
+            hist = self.order
+        self.pusher.fields_load_lattice(-hist, hist + extra, self.table, self.M, self.coeffs)
         self.n = 0
 
     def advance(self, steps: int, S: int | None = None):
