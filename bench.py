@@ -36,10 +36,11 @@ PEAK_FP64_TFLOPS = 78.6      # vector FP64, FMA counted as 2 flops
 PEAK_HBM_GBS = 8000.0
 
 KERNELS = {  # (kernel name in traces, sources it is built from)
-    "fp64": ("push_wave_kernel<3, 1, (Arith)0>", ("push_wave.hpp", "common.hpp")),
-    "fp64fast": ("push_fast_kernel<3, 1>", ("push_fast.hpp", "common.hpp")),
-    "fp32c": ("push_wave_fp32c_kernel<3, 1>", ("push_wave.hpp", "common.hpp")),
-    "ballot": ("push_tile_kernel<3, 256>", ("push_tile.hpp", "common.hpp")),
+    "fp64": ("push_wave_kernel<3, 1, (Arith)0, false>", ("push_wave.hpp", "common.hpp")),
+    "fp64fast": ("push_fast_kernel<3, 1, false, 0>", ("push_fast.hpp", "common.hpp")),
+    "fp64fast/occ5": ("push_fast_kernel<3, 1, false, 5>", ("push_fast.hpp", "common.hpp")),
+    "fp32c": ("push_wave_fp32c_kernel<3, 1, false>", ("push_wave.hpp", "common.hpp")),
+    "ballot": ("push_tile_kernel<3, 256, false>", ("push_tile.hpp", "common.hpp")),
 }
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "push_traffic.json")
 
@@ -105,7 +106,8 @@ class Pass:
     host-driven launches of S steps) or on a batch of runs (device-driven
     windows of S steps, each run stopping at its own step count)."""
 
-    def __init__(self, wl, S, precision, binning, predictor=None, fields="lattice"):
+    def __init__(self, wl, S, precision, binning, predictor=None, fields="lattice",
+                 occupancy=0):
         from paper_2102_10983_amd import runner
         self.wl = wl
         self.fill_events = []
@@ -124,6 +126,8 @@ class Pass:
                                         fields=fields)
             self.pusher = self.run.pusher
             self.a0 = wl.a0
+        if occupancy:
+            self.pusher.tune_set(occupancy=occupancy)
 
     def step(self, stream=None, events=None):
         import torch
@@ -204,6 +208,9 @@ def main():
     ap.add_argument("--periods", type=float, default=100.0)
     ap.add_argument("--order", type=int, default=3, choices=(1, 3, 5),
                     help="large/stress: temporal interpolation order p")
+    ap.add_argument("--occupancy", default="auto", choices=("auto", "0", "5"),
+                    help="register budget of the FP64_FAST push at orders 1, 3 (pic_tune): "
+                         "auto times one untimed pass with each and keeps the faster")
     ap.add_argument("--pb-width", type=float, default=0.0625,
                     help="cost step (log2 sub-steps) of the learned group order")
     ap.add_argument("--cpu-every", type=int, default=8)
@@ -261,6 +268,24 @@ def main():
         sys.exit(2)
     main_pass = Pass(wl, S, args.precision, args.binning, model, args.fields)
     main_pass.pb_width = args.pb_width
+    order = wl[0].order if isinstance(wl, list) else wl.order
+    occ_trials = None
+    occupancy = 0
+    if args.precision == "fp64fast" and order <= 3 and args.binning != "ballot":
+        if args.occupancy == "auto":
+            occ_trials = {}
+            for occ in (0, 5):
+                main_pass.pusher.tune_set(occupancy=occ)
+                main_pass.step()                          # warm-up with this budget
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                main_pass.step()
+                torch.cuda.synchronize()
+                occ_trials[occ] = (time.perf_counter() - t0) * 1e3
+            occupancy = min(occ_trials, key=occ_trials.get)
+        else:
+            occupancy = int(args.occupancy)
+        main_pass.pusher.tune_set(occupancy=occupancy)
     events = []
     elapsed = main_pass.time(args.steps, args.warmup, stream, events)
     counters = main_pass.pusher.counters()              # the last pass
@@ -271,10 +296,11 @@ def main():
     kernel_ms = sum(a.elapsed_time(b) for a, b in events)
     launches = len(events)
     launches_per_step = launches // args.steps
-    order = wl[0].order if isinstance(wl, list) else wl.order
     flops_step = algorithmic_flops(counters, order)
     achieved = flops_step * args.steps / (kernel_ms / 1e3) / 1e12
     key = "ballot" if args.binning == "ballot" else args.precision
+    if key == "fp64fast" and occupancy == 5:
+        key = "fp64fast/occ5"
     traffic = (measured_traffic(key, launches_per_step)
                if args.workload == "large" and args.fields == "lattice" and order == 3 else None)
     solve_ms = (sum(a.elapsed_time(b) for a, b in main_pass.fill_events) / args.steps
@@ -292,7 +318,8 @@ def main():
         for label, prec, binning, fields in legs:
             if prec == args.precision and binning == args.binning and fields == args.fields:
                 continue
-            p = Pass(wl, S, prec, binning, model if binning == "learned" else None, fields)
+            p = Pass(wl, S, prec, binning, model if binning == "learned" else None, fields,
+                     occupancy if prec == "fp64fast" else 0)
             p.pb_width = args.pb_width
             ev = [] if fields == "yee" else None
             t = p.time(args.steps, args.warmup, stream, ev)
@@ -327,6 +354,8 @@ def main():
                    "steps_per_launch": S, "sub_steps_per_pass": sub_per_step,
                    "mean_sub_steps_per_particle_step": sub_per_step / counters["steps"],
                    "n_star": counters["n_star"], "steps_by_k": counters["steps_by_k"][:9],
+                   "occupancy": occupancy,
+                   **({"occupancy_trial_ms": occ_trials} if occ_trials else {}),
                    **({"field_solve_ms": solve_ms} if solve_ms is not None else {})},
         "compare": compare,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,

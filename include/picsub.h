@@ -296,8 +296,8 @@ pic_status pic_run_counters(pic_ctx *ctx, int32_t run, pic_counters *cnt);
  * from then on every push kernel updates them after each completed step
  * of a live particle (a few square roots and divisions per sub-step, IEEE
  * in the PIC_FP64 kernels, bit-identical to a CPU loop).  on = 0: stop
- * updating (the values are kept).  Loading particles restarts them while
- * on; re-binning (pic_prebin) carries them with the particles; the
+ * updating (the values are kept).  Loading particles restarts them (on or
+ * off); re-binning (pic_prebin) carries them with the particles; the
  * autotuner's trials do not touch them; a captured graph keeps the setting
  * it was captured with; checkpoints do not include them.  The kernels
  * compile them in only while on. */
@@ -328,6 +328,12 @@ typedef struct {
                                 PIC_BIN_BALLOT (compaction kernel, FP64) */
     int32_t sort_sub;        /* position bins per cell of the load-time
                                 sort, 1..256 (next pic_particles_set) */
+    int32_t occupancy;       /* PIC_FP64_FAST at orders 1 and 3 with one
+                                wavefront per workgroup: 0 = the compiler's
+                                register budget (4 wavefronts per SIMD at
+                                order 3), 5 = a budget for 5 (a few
+                                registers spill; faster when few steps are
+                                sub-cycled, slower when many are) */
 } pic_tune;
 
 pic_status pic_tune_set(pic_ctx *ctx, const pic_tune *t);

@@ -65,7 +65,7 @@ struct pic_ctx {
     int32_t order = 3, kmax_all = 0, precision = PIC_FP64;
     hipStream_t stream = nullptr;
     int device = 0, ncu = 256;
-    pic_tune tune{1, 256, PIC_BIN_NONE, 64};
+    pic_tune tune{1, 256, PIC_BIN_NONE, 64, 0};
     bool have_particles = false;
     // particle store
     double *x = nullptr, *px = nullptr, *py = nullptr, *pz = nullptr;
@@ -296,11 +296,13 @@ PushArgs push_args(pic_ctx *ctx, int64_t n0, int32_t S)
 // DIAG: the trajectory diagnostics compiled in (only when they are switched
 // on, so the kernels without them keep their register budget)
 template <int P, int WPG, bool DIAG>
-void launch_wave(const PushArgs &a, int precision, hipStream_t s)
+void launch_wave(const PushArgs &a, int precision, int occupancy, hipStream_t s)
 {
     const dim3 grid(unsigned((a.ngroups + WPG - 1) / WPG)), block(64 * WPG);
     if (precision == PIC_FP64)
         push_wave_kernel<P, WPG, Arith::IEEE64, DIAG><<<grid, block, 0, s>>>(a);
+    else if (precision == PIC_FP64_FAST && occupancy == 5 && WPG == 1 && !DIAG && P <= 3)
+        push_fast_kernel<P, 1, false, 5><<<grid, block, 0, s>>>(a);
     else if (precision == PIC_FP64_FAST)
         push_fast_kernel<P, WPG, DIAG><<<grid, block, 0, s>>>(a);
     else
@@ -320,9 +322,9 @@ void launch_shape(const PushArgs &a, const pic_tune &t, int precision, int64_t s
         return;
     }
     switch (t.waves_per_group) {
-    case 2: launch_wave<P, 2, DIAG>(a, precision, s); break;
-    case 4: launch_wave<P, 4, DIAG>(a, precision, s); break;
-    default: launch_wave<P, 1, DIAG>(a, precision, s); break;
+    case 2: launch_wave<P, 2, DIAG>(a, precision, t.occupancy, s); break;
+    case 4: launch_wave<P, 4, DIAG>(a, precision, t.occupancy, s); break;
+    default: launch_wave<P, 1, DIAG>(a, precision, t.occupancy, s); break;
     }
 }
 
@@ -647,7 +649,8 @@ pic_status load_particles(pic_ctx *ctx, pic_mem mem, const double *x, const doub
                            ctx->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     }
-    if (e == hipSuccess && ctx->deph) {          // new particles: the diagnostics restart
+    if (e == hipSuccess && ctx->r0) {            // new particles: the diagnostics restart
+                                                  // (their values belong to slots)
         diag_init_kernel<<<grid_for(ctx->slots, 256, 8192), 256, 0, ctx->stream>>>(
             ctx->slots, ctx->px, ctx->py, ctx->pz, ctx->r0, ctx->rmax, ctx->work, ctx->werr);
         e = hipGetLastError();
@@ -1114,6 +1117,7 @@ pic_status pic_tune_set(pic_ctx *ctx, const pic_tune *t)
     if (t->binning == PIC_BIN_BALLOT && ctx->precision != PIC_FP64)
         return fail(ctx, PIC_E_ARG, "the tiled ballot push runs with PIC_FP64 only");
     if (t->sort_sub < 1 || t->sort_sub > 256) return fail(ctx, PIC_E_ARG, "sort_sub must be in [1, 256]");
+    if (t->occupancy != 0 && t->occupancy != 5) return fail(ctx, PIC_E_ARG, "occupancy must be 0 or 5");
     ctx->tune = *t;
     return PIC_OK;
 }
@@ -1173,10 +1177,13 @@ pic_status pic_autotune(pic_ctx *ctx, int32_t steps, int32_t reps, pic_tune *bes
     // candidates: wavefront kernels with 1, 2, 4 wavefronts per workgroup;
     // compaction kernel with tiles of 128, 256, 512 (FP64 only)
     std::vector<pic_tune> cand;
-    for (int w : {1, 2, 4}) cand.push_back(pic_tune{w, ctx->tune.tile, PIC_BIN_NONE, ctx->tune.sort_sub});
+    const pic_tune &cur = ctx->tune;
+    for (int w : {1, 2, 4}) cand.push_back(pic_tune{w, cur.tile, PIC_BIN_NONE, cur.sort_sub, 0});
+    if (ctx->precision == PIC_FP64_FAST && ctx->order <= 3)
+        cand.push_back(pic_tune{1, cur.tile, PIC_BIN_NONE, cur.sort_sub, 5});
     if (ctx->precision == PIC_FP64)
         for (int t : {128, 256, 512})
-            cand.push_back(pic_tune{ctx->tune.waves_per_group, t, PIC_BIN_BALLOT, ctx->tune.sort_sub});
+            cand.push_back(pic_tune{cur.waves_per_group, t, PIC_BIN_BALLOT, cur.sort_sub, 0});
     // snapshot of everything a trial changes
     const size_t n = size_t(ctx->slots);
     double *snap = nullptr;

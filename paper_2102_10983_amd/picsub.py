@@ -71,12 +71,12 @@ class Counters(C.Structure):
 
 class Tune(C.Structure):
     _fields_ = [("waves_per_group", C.c_int32), ("tile", C.c_int32), ("binning", C.c_int32),
-                ("sort_sub", C.c_int32)]
+                ("sort_sub", C.c_int32), ("occupancy", C.c_int32)]
 
     def as_dict(self):
         return {"waves_per_group": self.waves_per_group, "tile": self.tile,
                 "binning": {v: k for k, v in BINNING.items()}[self.binning],
-                "sort_sub": self.sort_sub}
+                "sort_sub": self.sort_sub, "occupancy": self.occupancy}
 
 
 _lib = None
@@ -388,11 +388,13 @@ class Pusher:
         self._check(self._lib.pic_tune_get(self._ctx, C.byref(t)))
         return t.as_dict()
 
-    def tune_set(self, waves_per_group=None, tile=None, binning=None, sort_sub=None):
+    def tune_set(self, waves_per_group=None, tile=None, binning=None, sort_sub=None,
+                 occupancy=None):
         cur = self.tune_get()
         t = Tune(waves_per_group=waves_per_group or cur["waves_per_group"],
                  tile=tile or cur["tile"], binning=BINNING[binning or cur["binning"]],
-                 sort_sub=sort_sub or cur["sort_sub"])
+                 sort_sub=sort_sub or cur["sort_sub"],
+                 occupancy=cur["occupancy"] if occupancy is None else occupancy)
         self._check(self._lib.pic_tune_set(self._ctx, C.byref(t)))
 
     def autotune(self, steps: int, reps: int = 1):

@@ -193,3 +193,37 @@ def test_checkpoint_resume_equals_uninterrupted_run(torch_gpu):
     with pytest.raises(picsub.PicError):
         other.pusher.state_import(blob)
     other.close()
+
+
+def test_diagnostics_in_a_captured_graph(torch_gpu):
+    """Trajectory diagnostics switched on before the capture run inside the
+    graph: replays give the eager values bit for bit (FP64); a captured
+    graph keeps its setting when the diagnostics are switched off later."""
+    from paper_2102_10983_amd import runner
+    wls = _small_batch(seed=12)
+    eager = runner.BatchRun(wls, S=29, precision="fp64", binning="none")
+    eager.reset()
+    eager.pusher.diag_track(True)
+    eager.run_all()
+    want_d = eager.pusher.dephasing_read()
+    want_w = eager.pusher.energy_read()
+    eager.close()
+    g = runner.BatchRun(wls, S=29, precision="fp64", binning="none")
+    g.reset()
+    g.pusher.diag_track(True)
+    g.capture()
+    for rep in range(2):
+        g.reset()                                  # tracking on: restarts the diagnostics
+        g.replay()
+        got_d = g.pusher.dephasing_read()
+        got_w = g.pusher.energy_read()
+        for a, b in zip(got_d + got_w, want_d + want_w):
+            assert np.array_equal(a, b), rep
+    g.pusher.diag_track(False)
+    g.reset()                                      # loading particles restarts them (off too)
+    assert not g.pusher.energy_read()[0].any()
+    g.replay()                                     # the graph still updates them
+    for a, b in zip(g.pusher.dephasing_read() + g.pusher.energy_read(), want_d + want_w):
+        assert np.array_equal(a, b)
+    g.pusher.graph_release()
+    g.close()

@@ -307,3 +307,28 @@ def test_fp32c_accuracy_envelope(torch_gpu, runner, order):
     res = compare(wl, wl.steps, d, np.arange(wl.num), 1e-3, g_ktrace=kt, flip_rel=1e-2)
     _say({k: v for k, v in res.items() if k != "oracle_counters"})
     assert res["p99_e_p"] < 1e-4 and res["max_e_x"] < 1e-6
+
+
+@pytest.mark.parametrize("order", [1, 3])
+def test_fp64fast_register_budget_changes_nothing(torch_gpu, runner, order):
+    """occupancy = 5 compiles the same arithmetic for 5 wavefronts per SIMD
+    (a few registers spill): the bits, counters and k trace are those of the
+    default budget."""
+    torch = torch_gpu
+    wl = W.make_workload("th", 3000, 100.0, 75, 500, 4, order, 0.01, 4.0, seed=41,
+                         theta=10.0 / 511.0)
+    out = []
+    for occ in (0, 5):
+        run = runner.DeviceRun(wl, S=wl.steps, binning="none", precision="fp64fast")
+        run.pusher.tune_set(occupancy=occ)
+        run.reset()
+        buf = torch.full((wl.steps, wl.num), -2, dtype=torch.int8, device="cuda")
+        run.pusher.ktrace_set(buf, 0, 0)
+        run.advance(wl.steps)
+        d = run.diag()
+        out.append((d, buf.cpu().numpy()))
+        run.close()
+    (d0, k0), (d5, k5) = out
+    for key in ("x", "px", "py", "pz", "k_last", "status"):
+        assert np.array_equal(d0[key], d5[key]), key
+    assert d0["counters"] == d5["counters"] and np.array_equal(k0, k5)

@@ -170,3 +170,33 @@ def test_standard_pic_large_case_sampled(torch_gpu):
                   fields=oracle_yee_fields(wl, wl.steps))
     _say({k: v for k, v in res.items() if k != "oracle_counters"})
     assert res["max_e_p"] < 1e-6
+
+
+def test_yee_on_one_run_of_a_batch(torch_gpu):
+    """pic_fields_yee_r on run 1 of a two-run context: that run's levels
+    equal the reference for its own grid and time step; run 0 is untouched."""
+    torch = torch_gpu
+    from oracle import yee_ref as Y
+    from paper_2102_10983_amd import picsub
+    rng = np.random.default_rng(77)
+    runs = []
+    for nc, nt in ((300, 75), (700, 150)):
+        dt = 2 * np.pi / nt
+        runs.append((0, picsub.make_params(ncells=nc, order=3, dx=1.01 * dt, dt=dt, psi_max=0.01,
+                                           ring_depth=60, precision="fp64", binning="none")))
+    p = picsub.Pusher(runs=runs)
+    M = 1013
+    table = rng.standard_normal(M)
+    tab = torch.from_numpy(table).cuda()
+    co = (7, 3, 1, 200, -202, 100)
+    p.fields_load_lattice_r(1, -1, 1, tab, M, co)
+    p.fields_yee(0, 50, tab, M, co[3], co[5], run=1)
+    prm = runs[1][1]
+    E0, B0 = _lattice_level(table, M, co, -1, prm.ncells)
+    El, Bl = Y.advance_lattice(E0, B0, prm.dx, prm.dt, 0, 50, table, co[3], co[5])
+    for m in (0, 17, 49):
+        e, b = p.fields_read(m, run=1)
+        assert np.array_equal(e, El[m]) and np.array_equal(b, Bl[m]), m
+    with pytest.raises(picsub.PicError):
+        p.fields_read(0, run=0)
+    p.close()
