@@ -119,45 +119,6 @@ __device__ __forceinline__ void boris(double qm, double dtp, double E, double B,
     pz = mz;
 }
 
-// 1 / b: hardware estimate refined by two Newton steps
-__device__ __forceinline__ double rcp_nr(double b)
-{
-    double r = __builtin_amdgcn_rcp(b);
-    double e = fma(-b, r, 1.0);
-    r = fma(r, e, r);
-    e = fma(-b, r, 1.0);
-    return fma(r, e, r);
-}
-
-// 1 / sqrt(a) for a >= 1: hardware estimate refined by two Newton steps
-__device__ __forceinline__ double rsq_nr(double a)
-{
-    double y = __builtin_amdgcn_rsq(a);
-    const double h = 0.5 * a;
-    double r = fma(-h * y, y, 0.5);
-    y = fma(y, r, y);
-    r = fma(-h * y, y, 0.5);
-    return fma(y, r, y);
-}
-
-// The same Boris update with the refined estimates in place of the IEEE
-// division and square root.
-__device__ __forceinline__ void boris_fast(double qm, double dtp, double E, double B, double &px,
-                                           double &py, double &pz)
-{
-    const double c = 0.5 * qm * dtp;
-    const double h = c * E;
-    const double mx = px, my = py + h, mz = pz;
-    const double ig = rsq_nr(1.0 + ((mx * mx + my * my) + mz * mz));
-    const double t = (c * B) * ig;
-    const double sz = (2.0 * t) * rcp_nr(1.0 + t * t);
-    const double ax = mx + my * t;
-    const double ay = my - mx * t;
-    px = mx + ay * sz;
-    py = (my - ax * sz) + h;
-    pz = mz;
-}
-
 __device__ __forceinline__ void two_sum(float a, float b, float &s, float &e)
 {
     s = a + b;

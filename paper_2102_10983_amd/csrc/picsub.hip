@@ -300,7 +300,7 @@ void launch_wave(const PushArgs &a, int precision, int occupancy, hipStream_t s)
 {
     const dim3 grid(unsigned((a.ngroups + WPG - 1) / WPG)), block(64 * WPG);
     if (precision == PIC_FP64)
-        push_wave_kernel<P, WPG, Arith::IEEE64, DIAG><<<grid, block, 0, s>>>(a);
+        push_wave_kernel<P, WPG, DIAG><<<grid, block, 0, s>>>(a);
     else if (precision == PIC_FP64_FAST && occupancy == 5 && WPG == 1 && !DIAG && P <= 3)
         push_fast_kernel<P, 1, false, 5><<<grid, block, 0, s>>>(a);
     else if (precision == PIC_FP64_FAST)

@@ -20,13 +20,12 @@
 
 namespace picsub {
 
-enum class Arith { IEEE64, FAST64 };
-
-template <int P, int WPG, Arith AR, bool DIAG = false>
+// IEEE FP64 throughout (PIC_FP64): the operations and their order are those
+// of the CPU oracle, so the results are bit-identical to it.
+template <int P, int WPG, bool DIAG = false>
 __global__ void __launch_bounds__(64 * WPG) push_wave_kernel(PushArgs a)
 {
     constexpr int STRIDE = 2 * (P + 1);
-    constexpr bool FAST = AR == Arith::FAST64;
     __shared__ double sE_all[WPG][(P + 1) * WWIN];
     __shared__ double sB_all[WPG][(P + 1) * WWIN];
     const int lane = threadIdx.x & 63;
@@ -50,17 +49,15 @@ __global__ void __launch_bounds__(64 * WPG) push_wave_kernel(PushArgs a)
 
     const int64_t s = int64_t(g) * 64 + lane;
     const bool mine = s - R.p_off < R.np;
-    double x = 0, px = 0, py = 0, pz = 0, ig = 1;   // x: absolute (IEEE) or node units (FAST)
+    double x = 0, px = 0, py = 0, pz = 0;
     int kold = 0;
     uint8_t status = PIC_PARTICLE_LOST;
     int64_t kt_u = -1;
     if (mine) {
         x = a.x[s];
-        if (FAST) x = (x - R.x_origin) / R.dx;
         px = a.px[s];
         py = a.py[s];
         pz = a.pz[s];
-        if (FAST) ig = rsq_nr(1.0 + ((px * px + py * py) + pz * pz));
         kold = a.kold[s];
         status = a.status[s];
         if (a.ktrace) {
@@ -83,7 +80,7 @@ __global__ void __launch_bounds__(64 * WPG) push_wave_kernel(PushArgs a)
         const int64_t n = n0 + st;
         Levels<P> lv;
         lv.at(slot0, st, R.D, R.ncells);
-        double xi = FAST ? x : (x - R.x_origin) / R.dx;
+        double xi = (x - R.x_origin) / R.dx;
         const bool live = status == PIC_PARTICLE_LIVE && xi >= 0.5 && xi < ncm1;
         const bool left = status == PIC_PARTICLE_LIVE && !live;
         cnt.lost += __popcll(__ballot(left));
@@ -105,15 +102,9 @@ __global__ void __launch_bounds__(64 * WPG) push_wave_kernel(PushArgs a)
             const double b0 = node_comb<P>(R.ringB, lv.off, cell, LB1);
             const double b1 = node_comb<P>(R.ringB, lv.off, cell + 1, LB1);
             Bd = (1.0 - wB) * b0 + wB * b1;
-            double psi0;
-            if (FAST) {
-                psi0 = fabs(c0 * Bd) * ig;
-                if (deph) gst = gamma_of(px, py, pz);
-            } else {
-                const double g0 = sqrt(1.0 + ((px * px + py * py) + pz * pz));
-                psi0 = fabs(c0 * Bd) / g0;
-                gst = g0;
-            }
+            const double g0 = sqrt(1.0 + ((px * px + py * py) + pz * pz));
+            const double psi0 = fabs(c0 * Bd) / g0;
+            gst = g0;
             double lim = R.psi_max;
             while (psi0 > lim && k < R.kmax) {
                 ++k;
@@ -149,7 +140,6 @@ __global__ void __launch_bounds__(64 * WPG) push_wave_kernel(PushArgs a)
         kold = k;
         const double dt_new = ldexp(R.dt, -2 * k);
         const double dt_old = ldexp(R.dt, -2 * ko);
-        const double rdx = ldexp(R.dtdx, -2 * k);
         if (k == 0) {
             // s = 1/2 is the time of level n: E's weights are (0, .., 0, 1)
             const double uE = xi - 0.5;
@@ -161,17 +151,10 @@ __global__ void __launch_bounds__(64 * WPG) push_wave_kernel(PushArgs a)
             const double E = (1.0 - wE) * e0 + wE * e1;
             const double dtp = 0.5 * (dt_old + dt_new);
             const double vb = deph ? py / gst : 0.0;
-            if (FAST) {
-                boris_fast(R.qm, dtp, E, Bd, px, py, pz);
-                ig = rsq_nr(1.0 + ((px * px + py * py) + pz * pz));
-                x = x + rdx * (px * ig);
-                if (deph) sw = sub_step_work((0.5 * R.qm) * dtp, E, vb, py * ig);
-            } else {
-                boris(R.qm, dtp, E, Bd, px, py, pz);
-                const double g2 = sqrt(1.0 + ((px * px + py * py) + pz * pz));
-                x = x + dt_new * (px / g2);
-                if (deph) sw = sub_step_work((0.5 * R.qm) * dtp, E, vb, py / g2);
-            }
+            boris(R.qm, dtp, E, Bd, px, py, pz);
+            const double g2 = sqrt(1.0 + ((px * px + py * py) + pz * pz));
+            x = x + dt_new * (px / g2);
+            if (deph) sw = sub_step_work((0.5 * R.qm) * dtp, E, vb, py / g2);
             done = true;
         } else {
             set_prio(prio + 2);
@@ -184,7 +167,7 @@ __global__ void __launch_bounds__(64 * WPG) push_wave_kernel(PushArgs a)
             double gcur = gst;                 // gamma of the momentum before the sub-step
             for (int j = 1; j <= nsub; ++j, Wk += STRIDE) {
                 if (j > 1) {
-                    xi = FAST ? x : (x - R.x_origin) / R.dx;
+                    xi = (x - R.x_origin) / R.dx;
                     if (!(xi >= 0.5 && xi < ncm1)) {
                         done = false;
                         break;
@@ -213,22 +196,12 @@ __global__ void __launch_bounds__(64 * WPG) push_wave_kernel(PushArgs a)
                 const double E = (1.0 - we) * e0 + we * e1;
                 const double dtp = j == 1 ? 0.5 * (dt_old + dt_new) : dt_new;
                 const double vb = deph ? py / gcur : 0.0;
-                if (FAST) {
-                    boris_fast(R.qm, dtp, E, B, px, py, pz);
-                    ig = rsq_nr(1.0 + ((px * px + py * py) + pz * pz));
-                    x = x + rdx * (px * ig);
-                    if (deph) {
-                        gcur = gamma_of(px, py, pz);
-                        sw += sub_step_work((0.5 * R.qm) * dtp, E, vb, py / gcur);
-                    }
-                } else {
-                    boris(R.qm, dtp, E, B, px, py, pz);
-                    const double g2 = sqrt(1.0 + ((px * px + py * py) + pz * pz));
-                    x = x + dt_new * (px / g2);
-                    if (deph) {
-                        sw += sub_step_work((0.5 * R.qm) * dtp, E, vb, py / g2);
-                        gcur = g2;
-                    }
+                boris(R.qm, dtp, E, B, px, py, pz);
+                const double g2 = sqrt(1.0 + ((px * px + py * py) + pz * pz));
+                x = x + dt_new * (px / g2);
+                if (deph) {
+                    sw += sub_step_work((0.5 * R.qm) * dtp, E, vb, py / g2);
+                    gcur = g2;
                 }
             }
             set_prio(prio);
@@ -244,7 +217,7 @@ __global__ void __launch_bounds__(64 * WPG) push_wave_kernel(PushArgs a)
     }
     if (mine) {
         if (moved) {
-            a.x[s] = FAST ? R.x_origin + x * R.dx : x;
+            a.x[s] = x;
             a.px[s] = px;
             a.py[s] = py;
             a.pz[s] = pz;
