@@ -340,11 +340,19 @@ pic_status pic_tune_set(pic_ctx *ctx, const pic_tune *t);
 pic_status pic_tune_get(const pic_ctx *ctx, pic_tune *t);
 
 /* Time `reps` device-driven windows of `steps` steps for each candidate
- * launch shape (1, 2, 4 wavefronts per workgroup; compaction tiles of
- * 128, 256, 512 with PIC_FP64), restoring the state after every trial,
- * and keep the fastest.  Requires sources on all runs. */
+ * launch shape (1, 2, 4 wavefronts per workgroup; the 5-wavefront register
+ * budget with PIC_FP64_FAST at orders 1 and 3; compaction tiles of 128,
+ * 256, 512 with PIC_FP64), restoring the state after every trial, and keep
+ * the fastest.  Requires sources on all runs.  The winner is remembered
+ * for the process under the configuration's signature (device, precision,
+ * order, k_max, steps, sort_sub and every run's particle count, grid, ring
+ * depth, dx, dt, psi_max, q/m and source coefficients; not the field
+ * values): a later call with the same signature applies it without trials
+ * (*ms_best is then the time measured when it was tuned).
+ * pic_autotune_forget clears that memory. */
 pic_status pic_autotune(pic_ctx *ctx, int32_t steps, int32_t reps,
                         pic_tune *best, double *ms_best);
+pic_status pic_autotune_forget(void);
 
 /* Number of 64-slot particle groups and the order in which the wavefront
  * kernels start them: order[i] is the group started i-th (a permutation;
@@ -455,7 +463,8 @@ pic_status pic_prebin(pic_ctx *ctx, const float *score, int32_t nbuckets, float 
  * copied).  The features need level n - 2 in the ring (always there for
  * order >= 2).  Each turn synchronises the stream; windows captured into a
  * graph run without it (they keep whatever order is current when they
- * run).  w_bf16 == NULL detaches.  Results never depend on it. */
+ * run), and no turns are taken while a captured graph is held.
+ * w_bf16 == NULL detaches.  Results never depend on it. */
 pic_status pic_predictor_set(pic_ctx *ctx, const uint16_t *w_bf16, const float *norm,
                              const float *run_a0, float width, int32_t every_M);
 

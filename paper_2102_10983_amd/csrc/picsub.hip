@@ -27,6 +27,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <vector>
@@ -427,6 +429,7 @@ pic_status read_counters(pic_ctx *ctx, int32_t run, pic_counters *cnt)
 pic_status predictor_turn(pic_ctx *ctx, int64_t n)
 {
     if (!ctx->pred_w || ctx->pred_every <= 0) return PIC_OK;
+    if (ctx->gexec) return PIC_OK;         // no re-binning while a captured graph is held
     if (ctx->pred_calls++ % ctx->pred_every != 0) return PIC_OK;
     pic_status st = pic_features(ctx, n, ctx->pred_a0.data(), ctx->pred_feat);
     if (st) return st;
@@ -1166,6 +1169,36 @@ int32_t pic_group_count(const pic_ctx *ctx)
     return ctx ? ctx->ngroups : 0;
 }
 
+namespace {
+// Winners of pic_autotune, per configuration signature, for the process.
+std::mutex tune_cache_mu;
+std::map<std::vector<int64_t>, std::pair<pic_tune, double>> tune_cache;
+
+std::vector<int64_t> tune_signature(const pic_ctx *ctx, int32_t steps)
+{
+    auto bits = [](double v) {
+        int64_t b;
+        std::memcpy(&b, &v, sizeof b);
+        return b;
+    };
+    std::vector<int64_t> k{ctx->device, ctx->precision, ctx->order, ctx->kmax_all, steps,
+                           ctx->nruns, ctx->tune.sort_sub};
+    for (const RunHost &R : ctx->runs) {
+        k.insert(k.end(), {R.np, R.prm.ncells, R.prm.ring_depth, bits(R.prm.dx), bits(R.prm.dt),
+                           bits(R.prm.psi_max), bits(R.prm.qm), R.M, R.co[0], R.co[1], R.co[2],
+                           R.co[3], R.co[4], R.co[5]});
+    }
+    return k;
+}
+}  // namespace
+
+pic_status pic_autotune_forget(void)
+{
+    std::lock_guard<std::mutex> lock(tune_cache_mu);
+    tune_cache.clear();
+    return PIC_OK;
+}
+
 pic_status pic_autotune(pic_ctx *ctx, int32_t steps, int32_t reps, pic_tune *best, double *ms_best)
 {
     CTX_CHECK(ctx);
@@ -1174,6 +1207,17 @@ pic_status pic_autotune(pic_ctx *ctx, int32_t steps, int32_t reps, pic_tune *bes
     if (st) return st;
     if (ctx->gexec) return fail(ctx, PIC_E_STATE, "release the captured graph before tuning");
     if (ctx->np == 0) return fail(ctx, PIC_E_STATE, "nothing to tune: no particles");
+    const std::vector<int64_t> sig = tune_signature(ctx, steps);
+    {
+        std::lock_guard<std::mutex> lock(tune_cache_mu);
+        const auto it = tune_cache.find(sig);
+        if (it != tune_cache.end()) {          // tuned before: no trials
+            ctx->tune = it->second.first;
+            if (best) *best = it->second.first;
+            if (ms_best) *ms_best = it->second.second;
+            return PIC_OK;
+        }
+    }
     // candidates: wavefront kernels with 1, 2, 4 wavefronts per workgroup;
     // compaction kernel with tiles of 128, 256, 512 (FP64 only)
     std::vector<pic_tune> cand;
@@ -1268,6 +1312,8 @@ pic_status pic_autotune(pic_ctx *ctx, int32_t steps, int32_t reps, pic_tune *bes
     ctx->tune = winner;
     if (best) *best = winner;
     if (ms_best) *ms_best = wbest;
+    std::lock_guard<std::mutex> lock(tune_cache_mu);
+    tune_cache[sig] = {winner, wbest};
     return PIC_OK;
 }
 

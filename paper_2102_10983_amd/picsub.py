@@ -35,7 +35,7 @@ EXPORTS = ("pic_create", "pic_destroy", "pic_last_error", "pic_particles_set",
            "pic_state_import", "pic_fields_yee", "pic_fields_yee_r", "pic_fields_read",
            "pic_fields_read_r", "pic_diag_track", "pic_dephasing_read",
            "pic_energy_read",
-           "pic_predictor_set")
+           "pic_predictor_set", "pic_autotune_forget")
 
 MLP_FEATURES = 8
 MLP_HIDDEN = 64
@@ -135,6 +135,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "pic_diag_track": ([vp, i32], C.c_int),
         "pic_energy_read": ([vp, C.c_int, vp, vp], C.c_int),
         "pic_predictor_set": ([vp, vp, vp, vp, C.c_float, i32], C.c_int),
+        "pic_autotune_forget": ([], C.c_int),
         "pic_dephasing_read": ([vp, C.c_int, vp, vp], C.c_int),
     }
     for name, (args, res) in sig.items():
@@ -144,6 +145,13 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     if path == LIB_PATH:
         _lib = L
     return L
+
+
+def autotune_forget():
+    """Clear the process-wide memory of autotuned launch shapes."""
+    st = load_library().pic_autotune_forget()
+    if st != 0:
+        raise PicError(st, "pic_autotune_forget failed")
 
 
 def _torch():

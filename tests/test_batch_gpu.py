@@ -227,3 +227,30 @@ def test_diagnostics_in_a_captured_graph(torch_gpu):
         assert np.array_equal(a, b)
     g.pusher.graph_release()
     g.close()
+
+
+def test_autotune_remembers_a_signature(torch_gpu):
+    """A second context of the same configuration gets the first one's
+    winner without trials (same time reported, no state touched); after
+    pic_autotune_forget it is timed again."""
+    import time
+    from paper_2102_10983_amd import picsub, runner
+    picsub.autotune_forget()
+    wls = _small_batch(seed=15)
+    a = runner.BatchRun(wls, S=40, precision="fp64fast")
+    a.reset()
+    best_a, ms_a = a.pusher.autotune(steps=40, reps=1)
+    a.close()
+    b = runner.BatchRun(wls, S=40, precision="fp64fast")
+    b.reset()
+    t0 = time.perf_counter()
+    best_b, ms_b = b.pusher.autotune(steps=40, reps=1)
+    cached_s = time.perf_counter() - t0
+    assert best_b == best_a and ms_b == ms_a
+    assert b.pusher.tune_get() == best_a
+    assert b.pusher.counters()["steps"] == 0
+    picsub.autotune_forget()
+    _, ms_c = b.pusher.autotune(steps=40, reps=1)
+    b.close()
+    _say(f"cached lookup {cached_s * 1e3:.2f} ms, tuned {ms_a:.3f} / {ms_c:.3f} ms per window")
+    assert ms_c != ms_a

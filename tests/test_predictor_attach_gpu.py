@@ -114,3 +114,23 @@ def test_predictor_set_arguments(torch_gpu):
     run.advance(50)
     assert run.diag()["counters"]["rebins"] == 2
     run.close()
+
+
+def test_attached_predictor_with_a_held_graph(torch_gpu):
+    """While a captured graph is held, eager windows run without the
+    predictor's turns (re-binning is not allowed then) instead of failing."""
+    from paper_2102_10983_amd import predictor, runner
+    model = predictor.Predictor.load()
+    wls = W.batch_case(seed=8, nruns=3, periods=2.0, p_range=(50, 800),
+                       a0_range=(5.0, 100.0), cells_range=(400, 700))
+    b = runner.BatchRun(wls, S=30, precision="fp64fast")
+    b.reset()
+    model.attach(b.pusher, [w.a0 for w in wls], every=1)
+    b.capture()
+    b.run_all()                                        # eager windows, graph held
+    assert b.diag()["counters"]["rebins"] == 0
+    b.pusher.graph_release()
+    b.reset()
+    b.run_all()
+    assert b.diag()["counters"]["rebins"] == b.windows
+    b.close()
