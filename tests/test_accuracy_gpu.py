@@ -79,3 +79,29 @@ def test_batch_runs(torch_gpu, run_index):
     _say(f"batch run {run_index} ({wl.name}, {wl.num} electrons):",
          {k: v for k, v in res.items() if k != "oracle_counters"})
     assert res["max_e_p"] < 1e-6     # the bar is 1e-5
+
+
+def test_benchmark_configuration_sampled(torch_gpu):
+    """Exactly what bench.py times on its default workload: 2^20 electrons,
+    a0 = 150, learned group order, the 5-wavefront register budget, 7500
+    steps in one launch; 2048 consecutive electrons against the oracle."""
+    torch = torch_gpu
+    from paper_2102_10983_amd import predictor, runner
+    from parity import compare
+    wl = W.large_case(seed=22)
+    run = runner.DeviceRun(wl, S=wl.steps, precision="fp64fast", binning="none")
+    run.pusher.tune_set(occupancy=5)
+    run.reset()
+    predictor.Predictor.load().prebin(run.pusher, wl.a0, n=0)
+    first = int(np.random.default_rng(23).integers(0, wl.num - 2048))
+    buf = torch.full((wl.steps, 2048), -2, dtype=torch.int8, device="cuda")
+    run.pusher.ktrace_set(buf, 0, first)
+    run.advance(wl.steps)
+    d = run.diag()
+    run.close()
+    idx = np.arange(first, first + 2048)
+    full = np.full((wl.steps, wl.num), -3, dtype=np.int8)
+    full[:, idx] = buf.cpu().numpy()
+    res = compare(wl, wl.steps, d, idx, TOL, g_ktrace=full, flip_rel=1e-9)
+    _say("benchmark configuration:", {k: v for k, v in res.items() if k != "oracle_counters"})
+    assert res["max_e_p"] < 1e-6     # the bar is 1e-5
