@@ -1169,6 +1169,8 @@ int32_t pic_group_count(const pic_ctx *ctx)
     return ctx ? ctx->ngroups : 0;
 }
 
+}  // extern "C"
+
 namespace {
 // Winners of pic_autotune, per configuration signature, for the process.
 std::mutex tune_cache_mu;
@@ -1191,6 +1193,8 @@ std::vector<int64_t> tune_signature(const pic_ctx *ctx, int32_t steps)
     return k;
 }
 }  // namespace
+
+extern "C" {
 
 pic_status pic_autotune_forget(void)
 {

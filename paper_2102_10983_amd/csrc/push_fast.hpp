@@ -235,14 +235,16 @@ __global__ void __launch_bounds__(64 * WPG)
         if (trace_now) {
             if (!live && kt_u >= 0) a.ktrace[kt_row * a.kt_count + kt_u] = -1;
         }
-        if (!lmask) {
-            for (int s2 = st + 1; s2 < S_run; ++s2) ktrace_put(a, kt_u, n0 + s2, -1);
-            break;
-        }
+        // A wavefront with no live lane left runs on to the end: the rest
+        // of each step then changes nothing but the (clamped, in-bounds)
+        // step-ahead window.  An early exit costs more: the compiler's phi
+        // copies and lane reads for it run on every step (4-10 % of the
+        // launch).
         const double fl = floor(x);
         const int cell = int(fl);
         // reference cell: the first live lane's
-        const int cref = __builtin_amdgcn_readlane(cell, __ffsll((unsigned long long)lmask) - 1);
+        const int cref =
+            __builtin_amdgcn_readlane(cell, (__ffsll((unsigned long long)lmask) - 1) & 63);
 
         // Step-ahead loads: the levels of step n+1 on the nodes any lane can
         // reach from this step's cells (all within rad of cref).

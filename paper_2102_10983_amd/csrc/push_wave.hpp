@@ -86,10 +86,9 @@ __global__ void __launch_bounds__(64 * WPG) push_wave_kernel(PushArgs a)
         cnt.lost += __popcll(__ballot(left));
         if (left) status = PIC_PARTICLE_LOST;
         if (!live) ktrace_put(a, kt_u, n, -1);
-        if (!__any(live)) {
-            for (int s2 = st + 1; s2 < S_run; ++s2) ktrace_put(a, kt_u, n0 + s2, -1);
-            break;
-        }
+        // A wavefront with no live lane left runs on to the end (every
+        // access below is behind a live lane); an early exit costs its phi
+        // copies on every step.
         // decision: B at (x_n, s = 1/2), gamma of the stored momentum
         int k = 0, cell = 0;
         double Bd = 0.0;

@@ -180,6 +180,24 @@ def test_lost_particles_match_oracle(torch_gpu, runner):
     assert res["oracle_counters"].lost == d["counters"]["lost"]
 
 
+@pytest.mark.parametrize("S", [25, 75])
+def test_lost_wavefronts_fp64fast(torch_gpu, runner, S):
+    """The same electrons in the FP64_FAST push (position order, so whole
+    wavefronts run out of live lanes in mid-launch and go on as no-ops):
+    k traces, flags and loss counts as in the oracle."""
+    from parity import compare
+    wl = W.make_workload("edge", 256, 30.0, 75, 160, 3, 3, 0.01, 1.0, seed=3)
+    wl.x0[:] = wl.x_origin + (150 + 8 * np.arange(256) / 256.0) * wl.dx
+    wl.x0[::7] = wl.x_origin + 0.25 * wl.dx
+    d, kt = _gpu_full(torch_gpu, runner, wl, wl.steps, S, binning="none",
+                      precision="fp64fast")
+    res = compare(wl, wl.steps, d, np.arange(wl.num), TOL32, g_ktrace=kt, flip_rel=1e-9)
+    _say(S, {k: v for k, v in res.items() if k != "oracle_counters"})
+    assert d["counters"]["lost"] == int((d["status"] != 0).sum()) >= 64
+    assert res["oracle_counters"].lost == d["counters"]["lost"]
+    assert (kt[-1] < 0).sum() >= 64
+
+
 def test_error_codes(torch_gpu):
     from paper_2102_10983_amd import picsub
     with pytest.raises(picsub.PicError) as e:
