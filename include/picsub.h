@@ -330,10 +330,10 @@ typedef struct {
                                 sort, 1..256 (next pic_particles_set) */
     int32_t occupancy;       /* PIC_FP64_FAST at orders 1 and 3 with one
                                 wavefront per workgroup: 0 = the compiler's
-                                register budget (4 wavefronts per SIMD at
-                                order 3), 5 = a budget for 5 (a few
-                                registers spill; faster when few steps are
-                                sub-cycled, slower when many are) */
+                                register budget (4 wavefronts per SIMD),
+                                5 = a budget for 5 (a few registers spill;
+                                which is faster depends on the workload,
+                                pic_autotune times both) */
 } pic_tune;
 
 pic_status pic_tune_set(pic_ctx *ctx, const pic_tune *t);

@@ -121,12 +121,12 @@ __device__ __forceinline__ double comb_lds(const double *p, int field, const W &
     return v;
 }
 
-// Register budget: at order 5 the compiler alone would take 169 VGPRs (3
-// wavefronts per SIMD); a budget for 4 costs a few spills and runs about
-// 25 % faster.  OCC > 0 asks for OCC wavefronts per SIMD (pic_tune).
+// Register budget: the compiler's own allocation (123 VGPRs at orders 3 and 5)
+// gives 4 wavefronts per SIMD; OCC > 0 asks for OCC wavefronts per SIMD
+// (pic_tune.occupancy), paid for with spills.
 template <int P, int WPG, bool DIAG = false, int OCC = 0>
 __global__ void __launch_bounds__(64 * WPG)
-    __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : (P == 5 ? 4 : 1)))) push_fast_kernel(PushArgs a)
+    __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1))) push_fast_kernel(PushArgs a)
 {
     constexpr int ROWS = 2 * (P + 1);                 // row 2j: E of level j, 2j+1: B
     constexpr int NPF = (ROWS * PF_NW + 63) / 64;     // window values per lane
