@@ -216,6 +216,13 @@ struct WaveCounts {
                 steps[kk] += __popcll(wballot(done & (k == kk)));
         }
     }
+    // the same for the lanes with k > 0 only
+    __device__ __forceinline__ void steps_heavy(bool done, int k)
+    {
+#pragma unroll
+        for (int kk = 1; kk <= PIC_K_MAX_LIMIT; ++kk)
+            steps[kk] += __popcll(wballot(done & (k == kk)));
+    }
     __device__ __forceinline__ void flush(uint64_t *__restrict__ slot, int lane) const
     {
         if (lane != 0) return;

@@ -123,8 +123,10 @@ __device__ __forceinline__ double comb_lds(const double *p, int field, const W &
 
 // Register budget: the compiler's own allocation (123 VGPRs at orders 3 and 5)
 // gives 4 wavefronts per SIMD; OCC > 0 asks for OCC wavefronts per SIMD
-// (pic_tune.occupancy), paid for with spills.
-template <int P, int WPG, bool DIAG = false, int OCC = 0>
+// (pic_tune.occupancy), paid for with spills.  KT: the k trace compiled in
+// (launches with a trace buffer attached); its per-step bookkeeping costs
+// about 5 % of a launch that does not record.
+template <int P, int WPG, bool DIAG = false, bool KT = true, int OCC = 0>
 __global__ void __launch_bounds__(64 * WPG)
     __attribute__((amdgpu_waves_per_eu(OCC > 0 ? OCC : 1))) push_fast_kernel(PushArgs a)
 {
@@ -178,13 +180,13 @@ __global__ void __launch_bounds__(64 * WPG)
         kold = a.kold[s];
         fold = kold < 0 ? -1.0 : ldexp(1.0, -2 * kold);
         status = a.status[s];
-        if (a.ktrace) {
+        if (KT && a.ktrace) {
             const int64_t u = a.perm[s] - a.kt_first;
             if (u >= 0 && u < a.kt_count) kt_u = u;
         }
     }
     bool moved = false;
-    const bool tracing = a.ktrace != nullptr;
+    const bool tracing = KT && a.ktrace != nullptr;
     constexpr bool deph = DIAG;   // trajectory diagnostics compiled in
     double r0v = 1.0, rmx = 0.0, wacc = 0.0, wem = 0.0;
     if (deph && mine) {
@@ -230,7 +232,7 @@ __global__ void __launch_bounds__(64 * WPG)
             if ((status == PIC_PARTICLE_LIVE) & !live) status = PIC_PARTICLE_LOST;
         }
         // k trace: the row of this step, if it is recorded (wave-uniform)
-        const bool trace_now = st >= kt_lo && st < kt_hi;
+        const bool trace_now = KT && st >= kt_lo && st < kt_hi;
         const int64_t kt_row = n - a.kt_n0;
         if (trace_now) {
             if (!live && kt_u >= 0) a.ktrace[kt_row * a.kt_count + kt_u] = -1;
@@ -288,7 +290,10 @@ __global__ void __launch_bounds__(64 * WPG)
             Bd = tent_fma(x - fl, b0, b1);
             psi0 = fabs(c0 * Bd) * ig;
         }
-        if (lmask & wballot(psi0 > psi_max)) {   // some lane sub-cycles
+        // lanes over the threshold: with kmax > 0 exactly the sub-cycled ones
+        const uint64_t omask = lmask & wballot(psi0 > psi_max);
+        const uint64_t hmask = kmax > 0 ? omask : 0;
+        if (omask) {
             if (live) {
                 double lim = psi_max;
                 while (psi0 > lim && k < kmax) {
@@ -402,8 +407,13 @@ __global__ void __launch_bounds__(64 * WPG)
                 if (!done) status = PIC_PARTICLE_LOST;
             }
         }
-        cnt.steps_done(done, k);
-        cnt.lost += __popcll(wballot(live & !done));
+        // a k = 0 step always completes; only sub-cycled lanes can leave the
+        // grid inside a step
+        cnt.steps[0] += __popcll(lmask & ~hmask);
+        if (hmask) {
+            cnt.steps_heavy(done, k);
+            cnt.lost += __popcll(wballot(live & !done));
+        }
         if (deph && done) {
             dephasing_update(rmx, r0v, px, py, pz);
             energy_close(wacc, wem, gst, gamma_of(px, py, pz), swork);
