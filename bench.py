@@ -36,7 +36,7 @@ PEAK_FP64_TFLOPS = 78.6      # vector FP64, FMA counted as 2 flops
 PEAK_HBM_GBS = 8000.0
 
 KERNELS = {  # (kernel name in traces, sources it is built from)
-    "fp64": ("push_wave_kernel<3, 1, false>", ("push_wave.hpp", "common.hpp")),
+    "fp64": ("push_wave_kernel<3, 1, false, false>", ("push_wave.hpp", "common.hpp")),
     "fp64fast": ("push_fast_kernel<3, 1, false, false, 0>", ("push_fast.hpp", "common.hpp")),
     "fp64fast/occ5": ("push_fast_kernel<3, 1, false, false, 5>", ("push_fast.hpp", "common.hpp")),
     "fp32c": ("push_wave_fp32c_kernel<3, 1, false>", ("push_wave.hpp", "common.hpp")),

@@ -301,17 +301,18 @@ template <int P, int WPG, bool DIAG>
 void launch_wave(const PushArgs &a, int precision, int occupancy, hipStream_t s)
 {
     const dim3 grid(unsigned((a.ngroups + WPG - 1) / WPG)), block(64 * WPG);
-    if (precision == PIC_FP64)
-        push_wave_kernel<P, WPG, DIAG><<<grid, block, 0, s>>>(a);
-    else if (precision == PIC_FP64_FAST && occupancy == 5 && WPG == 1 && !DIAG && P <= 3) {
+    if (precision == PIC_FP64) {
+        if (a.ktrace) push_wave_kernel<P, WPG, DIAG, true><<<grid, block, 0, s>>>(a);
+        else push_wave_kernel<P, WPG, DIAG, false><<<grid, block, 0, s>>>(a);
+    } else if (precision == PIC_FP64_FAST && occupancy == 5 && WPG == 1 && !DIAG && P <= 3) {
         if (a.ktrace) push_fast_kernel<P, 1, false, true, 5><<<grid, block, 0, s>>>(a);
         else push_fast_kernel<P, 1, false, false, 5><<<grid, block, 0, s>>>(a);
     } else if (precision == PIC_FP64_FAST) {
         if (a.ktrace) push_fast_kernel<P, WPG, DIAG, true><<<grid, block, 0, s>>>(a);
         else push_fast_kernel<P, WPG, DIAG, false><<<grid, block, 0, s>>>(a);
-    }
-    else
+    } else {
         push_wave_fp32c_kernel<P, WPG, DIAG><<<grid, block, 0, s>>>(a);
+    }
 }
 
 template <int P, bool DIAG>

@@ -22,7 +22,8 @@ namespace picsub {
 
 // IEEE FP64 throughout (PIC_FP64): the operations and their order are those
 // of the CPU oracle, so the results are bit-identical to it.
-template <int P, int WPG, bool DIAG = false>
+// KT: the k trace compiled in (launches with a trace buffer attached).
+template <int P, int WPG, bool DIAG = false, bool KT = true>
 __global__ void __launch_bounds__(64 * WPG) push_wave_kernel(PushArgs a)
 {
     constexpr int STRIDE = 2 * (P + 1);
@@ -60,7 +61,7 @@ __global__ void __launch_bounds__(64 * WPG) push_wave_kernel(PushArgs a)
         pz = a.pz[s];
         kold = a.kold[s];
         status = a.status[s];
-        if (a.ktrace) {
+        if (KT && a.ktrace) {
             const int64_t u = a.perm[s] - a.kt_first;
             if (u >= 0 && u < a.kt_count) kt_u = u;
         }
@@ -85,7 +86,7 @@ __global__ void __launch_bounds__(64 * WPG) push_wave_kernel(PushArgs a)
         const bool left = status == PIC_PARTICLE_LIVE && !live;
         cnt.lost += __popcll(__ballot(left));
         if (left) status = PIC_PARTICLE_LOST;
-        if (!live) ktrace_put(a, kt_u, n, -1);
+        if (KT && !live) ktrace_put(a, kt_u, n, -1);
         // A wavefront with no live lane left runs on to the end (every
         // access below is behind a live lane); an early exit costs its phi
         // copies on every step.
@@ -110,13 +111,14 @@ __global__ void __launch_bounds__(64 * WPG) push_wave_kernel(PushArgs a)
                 lim = lim * 4.0;
             }
             clamped = psi0 > lim;
-            ktrace_put(a, kt_u, n, int8_t(k));
+            if (KT) ktrace_put(a, kt_u, n, int8_t(k));
         }
         cnt.clamps += __popcll(__ballot(clamped));
         const bool heavy = live && k > 0;
+        const uint64_t hmask = __ballot(heavy);
         bool use_lds = false;
         int lo = 0;
-        if (__any(heavy)) {
+        if (hmask) {
             lo = max(wave_min(heavy ? cell - R.margin : INT_MAX), 0);
             const int hi = min(wave_max(heavy ? cell + R.margin : INT_MIN), R.ncells - 1);
             use_lds = hi - lo + 1 <= WWIN;
@@ -207,8 +209,13 @@ __global__ void __launch_bounds__(64 * WPG) push_wave_kernel(PushArgs a)
             if (!done) status = PIC_PARTICLE_LOST;
         }
         }
-        cnt.steps_done(done, k);
-        cnt.lost += __popcll(__ballot(live && !done));
+        // a k = 0 step always completes; only sub-cycled lanes can leave the
+        // grid inside a step
+        cnt.steps[0] += __popcll(__ballot(live) & ~hmask);
+        if (hmask) {
+            cnt.steps_heavy(done, k);
+            cnt.lost += __popcll(__ballot(live && !done));
+        }
         if (deph && done) {
             dephasing_update(rmx, r0v, px, py, pz);
             energy_close(wacc, wem, gst, gamma_of(px, py, pz), sw);
