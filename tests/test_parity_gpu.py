@@ -350,3 +350,29 @@ def test_fp64fast_register_budget_changes_nothing(torch_gpu, runner, order):
     for key in ("x", "px", "py", "pz", "k_last", "status"):
         assert np.array_equal(d0[key], d5[key]), key
     assert d0["counters"] == d5["counters"] and np.array_equal(k0, k5)
+
+
+@pytest.mark.parametrize("precision,occ", [("fp64fast", 0), ("fp64fast", 5), ("fp64", 0)])
+def test_trace_buffer_changes_nothing(torch_gpu, runner, precision, occ):
+    """A launch with a k-trace buffer attached runs a kernel with the trace
+    compiled in, one without runs a kernel without it: the same bits and
+    counters either way (thermal electrons, some sub-cycled, some lost)."""
+    torch = torch_gpu
+    wl = W.make_workload("th", 3000, 100.0, 75, 500, 4, 3, 0.01, 4.0, seed=43,
+                         theta=10.0 / 511.0)
+    out = []
+    for traced in (False, True):
+        run = runner.DeviceRun(wl, S=wl.steps, binning="none", precision=precision)
+        run.pusher.tune_set(occupancy=occ)
+        run.reset()
+        if traced:
+            buf = torch.full((wl.steps, wl.num), -2, dtype=torch.int8, device="cuda")
+            run.pusher.ktrace_set(buf, 0, 0)
+        run.advance(wl.steps)
+        out.append(run.diag())
+        run.close()
+    d0, d1 = out
+    for key in ("x", "px", "py", "pz", "k_last", "status"):
+        assert np.array_equal(d0[key], d1[key]), key
+    assert d0["counters"] == d1["counters"]
+    assert d0["counters"]["lost"] > 0 and d0["counters"]["steps_by_k"][1] > 0
