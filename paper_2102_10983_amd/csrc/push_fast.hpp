@@ -38,7 +38,7 @@ typedef const __attribute__((address_space(1))) double *gdptr;
 // weight table holds for (k = 0, j = 1).
 template <int P> struct HalfStepB;
 template <> struct HalfStepB<1> {
-    __device__ constexpr double operator[](int j) const { return 0.5; }
+    __device__ constexpr double operator[](int) const { return 0.5; }
 };
 template <> struct HalfStepB<3> {
     __device__ constexpr double operator[](int j) const

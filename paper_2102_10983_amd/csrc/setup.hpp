@@ -144,7 +144,7 @@ __global__ void scan_sums_kernel(const int32_t *__restrict__ v, int64_t nb, int3
     part[threadIdx.x] = s;
     __syncthreads();
     for (int o = 128; o >= 1; o >>= 1) {
-        if (threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
+        if (int(threadIdx.x) < o) part[threadIdx.x] += part[threadIdx.x + o];
         __syncthreads();
     }
     if (threadIdx.x == 0) sums[blockIdx.x] = part[0];
@@ -190,7 +190,7 @@ __global__ void scan_chunk_kernel(int32_t *__restrict__ v, int64_t nb, const int
     part[threadIdx.x] = s;
     __syncthreads();
     for (int off = 1; off < 256; off <<= 1) {
-        const int32_t w = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+        const int32_t w = int(threadIdx.x) >= off ? part[threadIdx.x - off] : 0;
         __syncthreads();
         part[threadIdx.x] += w;
         __syncthreads();
