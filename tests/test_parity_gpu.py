@@ -268,6 +268,12 @@ def test_fp64fast_small_case(torch_gpu, runner, order, S):
     res = compare(wl, wl.steps, d, np.arange(wl.num), TOL32, g_ktrace=kt, flip_rel=1e-9)
     _say({k: v for k, v in res.items() if k != "oracle_counters"})
     assert res["max_e_p"] < 1e-9     # rounding-level in practice
+    # the counters are the histogram of the kernel's own k trace (no electron is lost here)
+    g = d["counters"]
+    assert g["lost"] == 0
+    assert g["steps_by_k"][:9] == [int(np.sum(kt == k)) for k in range(9)]
+    assert g["sub_steps"] == int(np.sum(np.where(kt >= 0, 4 ** kt.astype(np.int64), 0)))
+    assert g["steps"] == int(np.sum(kt >= 0))
 
 
 def test_fp64fast_thermal_and_edges(torch_gpu, runner):
