@@ -121,9 +121,9 @@ __device__ __forceinline__ double comb_lds(const double *p, int field, const W &
     return v;
 }
 
-// Register budget: the compiler's own allocation (123 VGPRs at orders 3 and 5)
-// gives 4 wavefronts per SIMD; OCC > 0 asks for OCC wavefronts per SIMD
-// (pic_tune.occupancy), paid for with spills.  KT: the k trace compiled in
+// Register budget: the compiler's own allocation (94 VGPRs at order 1, 120 at
+// order 3, 124 at order 5) gives 5, 4 and 4 wavefronts per SIMD; OCC > 0 asks
+// for OCC wavefronts per SIMD (pic_tune.occupancy), paid for with spills.  KT: the k trace compiled in
 // (launches with a trace buffer attached); its per-step bookkeeping costs
 // about 5 % of a launch that does not record.
 template <int P, int WPG, bool DIAG = false, bool KT = true, int OCC = 0>
