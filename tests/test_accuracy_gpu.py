@@ -28,13 +28,16 @@ def torch_gpu():
     return torch
 
 
-def test_thermal_load_subsample(torch_gpu):
-    """2^20 thermal electrons, a0 = 150, 100 periods, learned order; 4096
+@pytest.mark.parametrize("num,psi", [(1 << 20, 0.01), (1 << 24, 0.003)],
+                         ids=["2p20-psi0.01", "2p24-psi0.003"])
+def test_thermal_load_subsample(torch_gpu, num, psi):
+    """Thermal electrons (10 keV) over 200 wavelengths, a0 = 150, 100 periods,
+    learned order: 2^20 at Psi_max = 0.01 and the full 2^24 at 0.003; 4096
     consecutive electrons (caller order) checked against the oracle."""
     torch = torch_gpu
     from paper_2102_10983_amd import predictor, runner
     from parity import compare
-    wl = W.stress_case(num=1 << 20)
+    wl = W.stress_case(num=num, psi_max=psi)
     run = runner.DeviceRun(wl, S=wl.steps, precision="fp64fast", binning="none")
     run.reset()
     predictor.Predictor.load().prebin(run.pusher, wl.a0, n=0)
@@ -48,7 +51,7 @@ def test_thermal_load_subsample(torch_gpu):
     full = np.full((wl.steps, wl.num), -3, dtype=np.int8)
     full[:, idx] = buf.cpu().numpy()
     res = compare(wl, wl.steps, d, idx, TOL, g_ktrace=full, flip_rel=1e-9)
-    _say("thermal 2^20:", {k: v for k, v in res.items() if k != "oracle_counters"})
+    _say(f"thermal {num} psi {psi}:", {k: v for k, v in res.items() if k != "oracle_counters"})
     assert res["max_e_p"] < 1e-6     # the bar is 1e-5
 
 
