@@ -191,9 +191,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="large", choices=("large", "batch", "stress"),
+    ap.add_argument("--workload", default="large", choices=("large", "batch", "stress", "predictor"),
                     help="large: the default single run; batch: 64 uneven runs; stress: "
-                         "thermal electrons over 200 wavelengths")
+                         "thermal electrons over 200 wavelengths; predictor: 2^22 electrons at "
+                         "rest on 16384 cells, the learned-binning workload")
     ap.add_argument("--seed", type=int, default=22, choices=(20, 21, 22))
     ap.add_argument("--psi", type=float, default=0.01, help="psi_max of the stress workload")
     ap.add_argument("--S", type=int, default=0,
@@ -204,7 +205,8 @@ def main():
                          "(perfectly propagating PIC) or made by the Yee solver (standard PIC)")
     ap.add_argument("--binning", default="learned", choices=("none", "ballot", "learned"))
     ap.add_argument("--num", type=int, default=0,
-                    help="electrons (large: 2^20, stress: 2^24; batch: scale factor x 1e6)")
+                    help="electrons (large: 2^20, stress: 2^24, predictor: 2^22; batch: scale "
+                         "factor x 1e6)")
     ap.add_argument("--periods", type=float, default=100.0)
     ap.add_argument("--order", type=int, default=3, choices=(1, 3, 5),
                     help="large/stress: temporal interpolation order p")
@@ -246,6 +248,11 @@ def main():
         wdesc = (f"plane wave a0={wl.a0:g}, {wl.num} electrons at rest over 8 lambda, T/dt=75, "
                  f"dx=1.01 c dt, {wl.ncells} cells, {wl.steps} steps, order {wl.order}, "
                  f"psi_max {wl.psi_max}")
+    elif args.workload == "predictor":
+        wl = W.predictor_case(num=args.num or (1 << 22), periods=args.periods, order=args.order)
+        steps_max = wl.steps
+        wdesc = (f"plane wave a0=150, {wl.num} electrons at rest over 16 lambda, T/dt=75, "
+                 f"{wl.ncells} cells, {wl.steps} steps, order {wl.order}, psi_max {wl.psi_max}")
     elif args.workload == "stress":
         wl = W.stress_case(psi_max=args.psi, num=args.num or (1 << 24), periods=args.periods,
                            order=args.order)

@@ -216,6 +216,14 @@ def large_case(seed: int = 22, num: int = 1 << 20, periods: float = 100.0,
                          periods, order, 0.01, 8.0, seed=seed)
 
 
+def predictor_case(num: int = 1 << 22, periods: float = 100.0, order: int = 3) -> Workload:
+    """The learned-binning workload: 2^22 electrons at rest over 16
+    wavelengths in an a0 = 150 plane wave, T/dt = 75, 16384 cells, 100
+    periods, 3rd order, psi_max = 0.01."""
+    return make_workload(f"predictor a0=150 P={num} cells=16384", num, 150.0, 75, 16384,
+                         periods, order, 0.01, 16.0, seed=9)
+
+
 def stress_case(psi_max: float = 0.01, num: int = 1 << 24, periods: float = 100.0,
                 order: int = 3) -> Workload:
     """2^24 thermal electrons (10 keV) over 200 wavelengths, a0 = 150,

@@ -108,3 +108,28 @@ def test_benchmark_configuration_sampled(torch_gpu):
     res = compare(wl, wl.steps, d, idx, TOL, g_ktrace=full, flip_rel=1e-9)
     _say("benchmark configuration:", {k: v for k, v in res.items() if k != "oracle_counters"})
     assert res["max_e_p"] < 1e-6     # the bar is 1e-5
+
+
+def test_predictor_workload_sampled(torch_gpu):
+    """The learned-binning workload: 2^22 electrons at rest over 16
+    wavelengths, a0 = 150, 16384 cells, 100 periods in one launch, learned
+    order; 2048 consecutive electrons against the oracle."""
+    torch = torch_gpu
+    from paper_2102_10983_amd import predictor, runner
+    from parity import compare
+    wl = W.predictor_case()
+    run = runner.DeviceRun(wl, S=wl.steps, precision="fp64fast", binning="none")
+    run.reset()
+    predictor.Predictor.load().prebin(run.pusher, wl.a0, n=0)
+    first = int(np.random.default_rng(29).integers(0, wl.num - 2048))
+    buf = torch.full((wl.steps, 2048), -2, dtype=torch.int8, device="cuda")
+    run.pusher.ktrace_set(buf, 0, first)
+    run.advance(wl.steps)
+    d = run.diag()
+    run.close()
+    idx = np.arange(first, first + 2048)
+    full = np.full((wl.steps, wl.num), -3, dtype=np.int8)
+    full[:, idx] = buf.cpu().numpy()
+    res = compare(wl, wl.steps, d, idx, TOL, g_ktrace=full, flip_rel=1e-9)
+    _say("predictor workload:", {k: v for k, v in res.items() if k != "oracle_counters"})
+    assert res["max_e_p"] < 1e-6     # the bar is 1e-5
