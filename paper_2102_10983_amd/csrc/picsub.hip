@@ -296,7 +296,8 @@ PushArgs push_args(pic_ctx *ctx, int64_t n0, int32_t S)
 }
 
 // DIAG: the trajectory diagnostics compiled in (only when they are switched
-// on, so the kernels without them keep their register budget)
+// on, so the kernels without them keep their register budget); the k trace
+// is compiled in only for launches with a trace buffer attached.
 template <int P, int WPG, bool DIAG>
 void launch_wave(const PushArgs &a, int precision, int occupancy, hipStream_t s)
 {
