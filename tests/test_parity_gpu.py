@@ -411,3 +411,37 @@ def test_trace_buffer_changes_nothing(torch_gpu, runner, precision, occ):
         assert np.array_equal(d0[key], d1[key]), key
     assert d0["counters"] == d1["counters"]
     assert d0["counters"]["lost"] > 0 and d0["counters"]["steps_by_k"][1] > 0
+
+
+@pytest.mark.parametrize("case", range(12))
+def test_random_configurations(torch_gpu, runner, case):
+    """Seeded random configurations over the method's parameters: a0
+    log-uniform in [1, 150] (in [30, 150] for cases 8-11, where steps
+    sub-cycle deeply), order 1/3/5, Psi_max in {0.003, 0.01, 0.03},
+    T/dt in {40, 75, 150}, electrons at rest or thermal, 0.5-3 wavelengths,
+    2-5 periods, one launch or launches of 37 steps.  The IEEE push is held
+    to 1e-12 and the fast push to 1e-5 against the oracle (k-flip protocol)."""
+    from parity import compare
+    rng = np.random.default_rng(1000 + case)
+    a0 = float(np.exp(rng.uniform(np.log(30.0) if case >= 8 else 0.0, np.log(150.0))))
+    order = int(rng.choice([1, 3, 5]))
+    psi = float(rng.choice([0.003, 0.01, 0.03]))
+    n_t = int(rng.choice([40, 75, 150]))
+    periods = float(rng.uniform(2.0, 5.0))
+    theta = 10.0 / 511.0 if rng.integers(0, 2) else 0.0
+    num = int(rng.integers(700, 2500))
+    span = float(rng.uniform(0.5, 3.0))
+    ncells = int((span + periods + 6.0) * n_t / 1.01) + 16
+    wl = W.make_workload(f"random {case}", num, a0, n_t, ncells, periods, order, psi, span,
+                         seed=case, theta=theta)
+    S = wl.steps if case % 2 == 0 else 37
+    _say(f"case {case}: a0={a0:.3g} p={order} psi={psi} T/dt={n_t} theta={theta:.3g} "
+         f"num={num} steps={wl.steps} S={S}")
+    d, kt = _gpu_full(torch_gpu, runner, wl, wl.steps, S, binning="none", precision="fp64")
+    res = compare(wl, wl.steps, d, np.arange(wl.num), TOL64, g_ktrace=kt)
+    d2, kt2 = _gpu_full(torch_gpu, runner, wl, wl.steps, S, binning="none",
+                        precision="fp64fast")
+    res2 = compare(wl, wl.steps, d2, np.arange(wl.num), TOL32, g_ktrace=kt2, flip_rel=1e-9)
+    _say("  ieee", {k: v for k, v in res.items() if k != "oracle_counters"})
+    _say("  fast", {k: v for k, v in res2.items() if k != "oracle_counters"})
+    assert res["flips"] == 0 and res["bitwise"] == wl.num
