@@ -249,7 +249,8 @@ __device__ __forceinline__ void flush_wave(Counts &c, uint64_t *__restrict__ slo
 }
 
 // Issue priority of a wavefront: base (0 or 1) from the group's predicted
-// load, + 2 inside sub-step loops.
+// load, + 2 inside the sub-step loops of the IEEE and compaction kernels (the
+// fast kernel keeps its base priority there: raising it made it slower).
 __device__ __forceinline__ void set_prio(int p)
 {
     switch (p) {

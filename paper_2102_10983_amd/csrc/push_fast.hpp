@@ -367,7 +367,6 @@ __global__ void __launch_bounds__(64 * WPG)
                 if (deph) swork = sub_step_work(c1, Ek, vb, py * ig);
                 done = true;
             } else {
-                set_prio(prio + 2);
                 const int nsub = 1 << (2 * k);
                 const double cn = 0.5 * qm * dt_new;
                 const double *Wk = a.wtab + wtab_offset(k) * STRIDE;
@@ -403,7 +402,6 @@ __global__ void __launch_bounds__(64 * WPG)
                     x = fma(rdx, px * ig, x);
                     if (deph) swork += sub_step_work(j == 1 ? c1 : cn, Es, vb, py * ig);
                 }
-                set_prio(prio);
                 if (!done) status = PIC_PARTICLE_LOST;
             }
         }
