@@ -137,6 +137,25 @@ def test_standard_pic_fp64_bitwise(torch_gpu, S, binning):
     assert d["counters"]["sub_steps"] == c.sub_steps and d["counters"]["n_star"] == c.n_star
 
 
+@pytest.mark.parametrize("order,S", [(1, 1500), (5, 1500), (5, 16)])
+def test_standard_pic_other_orders(torch_gpu, order, S):
+    """Yee levels at 1st and 5th order: the IEEE push bit-identical to the
+    oracle on the reference's levels, the fast push within rounding."""
+    from paper_2102_10983_amd import runner
+    from parity import compare, oracle_yee_fields
+    wl = W.small_case(order=order)
+    fs = oracle_yee_fields(wl, wl.steps)
+    d, kt, _ = _run(torch_gpu, runner, wl, S, "fp64")
+    res = compare(wl, wl.steps, d, np.arange(wl.num), TOL64, g_ktrace=kt, fields=fs)
+    _say(f"standard PIC order {order} S={S} ieee:", {k: v for k, v in res.items() if k != "oracle_counters"})
+    assert res["flips"] == 0 and res["bitwise"] == wl.num
+    d2, kt2, _ = _run(torch_gpu, runner, wl, S, "fp64fast")
+    res2 = compare(wl, wl.steps, d2, np.arange(wl.num), TOL32, g_ktrace=kt2, fields=fs,
+                   flip_rel=1e-9)
+    _say(f"standard PIC order {order} S={S} fast:", {k: v for k, v in res2.items() if k != "oracle_counters"})
+    assert res2["max_e_p"] < 1e-9
+
+
 def test_standard_pic_fp64fast_small_and_thermal(torch_gpu):
     from paper_2102_10983_amd import runner
     from parity import compare, oracle_yee_fields
