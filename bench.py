@@ -39,7 +39,8 @@ KERNELS = {  # (kernel name in traces, sources it is built from)
     "fp64": ("push_wave_kernel<3, 1, false, false>", ("push_wave.hpp", "common.hpp")),
     "fp64fast": ("push_fast_kernel<3, 1, false, false, 0>", ("push_fast.hpp", "common.hpp")),
     "fp64fast/occ5": ("push_fast_kernel<3, 1, false, false, 5>", ("push_fast.hpp", "common.hpp")),
-    "fp32c": ("push_wave_fp32c_kernel<3, 1, false>", ("push_wave.hpp", "common.hpp")),
+    "fp32c": ("push_wave_fp32c_kernel<3, 1, false>", ("push_f32c.hpp", "push_fast.hpp",
+                                                        "common.hpp")),
     "ballot": ("push_tile_kernel<3, 256, false>", ("push_tile.hpp", "common.hpp")),
 }
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "push_traffic.json")

@@ -65,12 +65,15 @@ typedef enum { PIC_MEM_HOST = 0, PIC_MEM_DEVICE = 1 } pic_mem;
 typedef enum {
     PIC_FP64 = 0,       /* IEEE FP64 in the operation order of the equations:
                            bit-identical to a plain scalar implementation */
-    PIC_FP32_COMP = 1,  /* k = 0 steps in FP32 (FP32 fields and Boris update,
-                           p as FP32 hi/lo pairs with TwoSum, x as node index +
-                           FP32 fraction + carry); FP64 weights and sub-cycled
-                           steps.  Not within 1e-5 of FP64 for ultra-
-                           relativistic electrons (gamma amplifies FP32
-                           rounding of the transverse force) */
+    PIC_FP32_COMP = 1,  /* k = 0 steps in FP32: the Boris update (Sec. III)
+                           formed as cancellation-free increments added to p
+                           held as FP32 (hi, lo) pairs by TwoSum, x as node
+                           index + FP32 fraction + carry; FP64 fields,
+                           weights, decision (Sec. IV) and sub-cycled steps.
+                           Within 1e-5 of FP64 except on electrons whose
+                           trajectory is as sensitive as a 1e-10 relative
+                           change of the initial position (a long ride
+                           ending next to a stopping point) */
     PIC_FP64_FAST = 2   /* FP64 with fused multiply-adds, the hardware
                            reciprocal / rsqrt estimates refined by one Newton
                            step, positions in node units, 1/gamma reused by

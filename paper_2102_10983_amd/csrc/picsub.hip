@@ -40,6 +40,7 @@
 #include "setup.hpp"
 #include "mlp.hpp"
 #include "push_fast.hpp"
+#include "push_f32c.hpp"
 #include "fields_yee.hpp"
 
 using namespace picsub;

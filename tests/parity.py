@@ -73,13 +73,14 @@ def errors(gx, gpx, gpy, gpz, st: O.State, x0):
 
 
 def compare(wl, steps, gdiag, idx, tol, g_ktrace=None, order=None, psi_max=None,
-            flip_rel=1e-9, fields=None):
+            flip_rel=1e-9, fields=None, keep_each=False):
     """Compare device results (caller order, full arrays) on particles idx.
 
     flip_rel bounds how far from a threshold psi_max 4^k the first differing
     decision of a particle may lie (relative): rounding-level for the FP64
     path, the state difference the FP32 path is allowed for fp32c.
-    Returns a dict of statistics; raises AssertionError on a violation."""
+    Returns a dict of statistics (with keep_each, also the per-particle
+    e_p under "e_p_each"); raises AssertionError on a violation."""
     idx = np.asarray(idx)
     st, cnt, kt, pt = oracle_run(wl, steps, idx, order=order, psi_max=psi_max,
                                  trace=g_ktrace is not None, fields=fields)
@@ -93,18 +94,23 @@ def compare(wl, steps, gdiag, idx, tol, g_ktrace=None, order=None, psi_max=None,
         if out["flips"]:
             # every flip must sit at a threshold: psi0 / psi_max within
             # rounding of 4^k at the first differing step
+            worst = 0.0
             for c in np.nonzero(~same)[0]:
                 s0 = int(np.argmax(gk[:, c] != kt[:, c]))
                 r = pt[s0, c]
                 kk = max(int(gk[s0, c]), int(kt[s0, c]))
                 assert r > 0 and abs(r / 4.0 ** (kk - 1) - 1) < flip_rel, (c, s0, r, gk[s0, c],
                                                                            kt[s0, c])
+                worst = max(worst, abs(r / 4.0 ** (kk - 1) - 1))
+            out["worst_flip"] = worst
             fst, _, _, _ = oracle_run(wl, steps, idx[~same], order=order, psi_max=psi_max,
                                       forced_k=np.ascontiguousarray(gk[:, ~same]),
                                       fields=fields)
             st.x[~same], st.px[~same], st.py[~same], st.pz[~same] = fst.x, fst.px, fst.py, fst.pz
             st.status[~same] = fst.status
     e_p, e_x = errors(gx, gpx, gpy, gpz, st, wl.x0[idx])
+    if keep_each:
+        out["e_p_each"] = e_p
     out["max_e_p"] = float(e_p.max()) if len(idx) else 0.0
     out["max_e_x"] = float(e_x.max()) if len(idx) else 0.0
     if len(idx):
@@ -117,3 +123,17 @@ def compare(wl, steps, gdiag, idx, tol, g_ktrace=None, order=None, psi_max=None,
     assert out["max_e_p"] <= tol and out["max_e_x"] <= tol, out
     out["oracle_counters"] = cnt
     return out
+
+
+def conditioning(wl, steps, idx, rel=1e-10, order=None, psi_max=None):
+    """Sensitivity of the FP64 oracle's own trajectories: e_p between the
+    oracle run from x0 and the run from x0 (1 + rel), per particle of idx.
+    A path whose arithmetic acts on a trajectory like a perturbation of
+    that size cannot be held closer than this to the oracle on that
+    particle."""
+    idx = np.asarray(idx)
+    st, _, _, _ = oracle_run(wl, steps, idx, order=order, psi_max=psi_max)
+    st2 = O.State(wl.x0[idx] * (1.0 + rel), wl.p0[0][idx], wl.p0[1][idx], wl.p0[2][idx])
+    O.push(oracle_params(wl, order, psi_max), oracle_fields(wl), st2, 0, steps)
+    e_p, _ = errors(st2.x, st2.px, st2.py, st2.pz, st, wl.x0[idx])
+    return e_p

@@ -314,34 +314,31 @@ def test_fp64fast_large_case_sampled(torch_gpu, runner, seed):
 
 
 # ---------------------------------------------------------------------------
-# FP32 bulk with compensated state, FP64 sub-cycled steps: accuracy report.
-# For ultra-relativistic electrons the transverse force is a cancellation
-# of size E / gamma, so FP32 rounding of the fields and of the rotation is
-# amplified by gamma; this path does not reach 1e-5 on the worst electrons
-# (those near a stopping point at the end, where |p| ~ 1).  The envelope
-# asserted here is what it does reach.
+# FP32-compensated path (k = 0 steps in FP32 with compensated state, FP64
+# decision and sub-cycled steps) against the FP64 oracle at 1e-5.
 # ---------------------------------------------------------------------------
+def _fp32c_report(tag, res):
+    _say(tag, {k: v for k, v in res.items() if k not in ("oracle_counters", "e_p_each")})
+
+
 @pytest.mark.parametrize("order", [1, 3])
-def test_fp32c_accuracy_envelope(torch_gpu, runner, order):
+def test_fp32c_small_case(torch_gpu, runner, order):
+    """1024 electrons, a0 = 10, 20 periods: every electron within 1e-5 of
+    the FP64 oracle on p and x (k-flip protocol, flips within FLIP32 of a
+    threshold)."""
     _say(f"fp32c small case order={order}")
     from parity import compare
     wl = W.small_case(order=order)
     d, kt = _gpu_full(torch_gpu, runner, wl, wl.steps, wl.steps, binning="none",
                       precision="fp32c")
-    res = compare(wl, wl.steps, d, np.arange(wl.num), 1e-3, g_ktrace=kt, flip_rel=1e-2)
-    _say({k: v for k, v in res.items() if k != "oracle_counters"})
-    assert res["p99_e_p"] < 1e-4 and res["max_e_x"] < 1e-6
+    res = compare(wl, wl.steps, d, np.arange(wl.num), TOL32, g_ktrace=kt, flip_rel=FLIP32)
+    _fp32c_report(f"fp32c small case order={order}:", res)
+    assert res["max_e_gamma"] <= TOL32
 
 
-@pytest.mark.parametrize("seed", [20, 21, 22])
-def test_fp32c_large_case_errors(torch_gpu, runner, seed):
-    """The FP32-compensated path on the large case (2^20 electrons at rest,
-    a0 in {30, 100, 150}, 100 periods, one launch): errors on gamma, p_x and
-    x against the FP64 oracle for 2048 sampled electrons, reported beside
-    the FP64 path's bar.  The envelope asserted is what this path reaches."""
-    torch = torch_gpu
+def _fp32c_large(torch, runner, seed, precision="fp32c"):
     wl = W.large_case(seed=seed)
-    run = runner.DeviceRun(wl, S=wl.steps, binning="none", precision="fp32c")
+    run = runner.DeviceRun(wl, S=wl.steps, binning="none", precision=precision)
     run.reset()
     first = int(np.random.default_rng(seed + 100).integers(0, wl.num - 2048))
     idx = np.arange(first, first + 2048)
@@ -353,13 +350,31 @@ def test_fp32c_large_case_errors(torch_gpu, runner, seed):
     run.close()
     full = np.full((wl.steps, wl.num), -3, dtype=np.int8)
     full[:, idx] = kt
-    from parity import compare
-    # FP32 drift near stopping points moves psi0 by more than rounding, so a
-    # k decision may differ away from a threshold: every differing electron
-    # is replayed by the oracle with the device's k sequence
-    res = compare(wl, wl.steps, d, idx, 1e-2, g_ktrace=full, flip_rel=1e9)
-    _say(f"fp32c large case a0={wl.a0}:", {k: v for k, v in res.items() if k != "oracle_counters"})
-    assert res["p99_e_p"] < 1e-3 and res["max_e_x"] < 1e-3
+    return wl, d, full, idx
+
+
+@pytest.mark.parametrize("seed", [20, 21, 22])
+def test_fp32c_large_case(torch_gpu, runner, seed):
+    """2^20 electrons at rest, a0 in {30, 100, 150}, 100 periods, one launch;
+    2048 sampled electrons against the FP64 oracle, errors on gamma, p_x and
+    x reported.  Every electron is within 1e-5 on p and x, except electrons
+    whose FP64 trajectory is itself that sensitive: those must be within
+    their own oracle response to a 1e-10 relative change of x0 (the size of
+    perturbation the FP32 increments amount to, measured with the float32
+    model of the k = 0 step in tests/fp32_model.py).  p99 of e_p <= 1e-6."""
+    _say(f"fp32c large case seed={seed}")
+    from parity import compare, conditioning
+    wl, d, full, idx = _fp32c_large(torch_gpu, runner, seed)
+    res = compare(wl, wl.steps, d, idx, math.inf, g_ktrace=full, flip_rel=FLIP32, keep_each=True)
+    e_p = res["e_p_each"]
+    kappa = conditioning(wl, wl.steps, idx)
+    over = e_p > TOL32
+    _fp32c_report(f"fp32c large case a0={wl.a0}:", res)
+    _say(f"  over 1e-5: {int(over.sum())} electrons, their e_p {e_p[over]}, oracle response "
+         f"{kappa[over]}; electrons with response > 1e-5: {int((kappa > TOL32).sum())}")
+    assert np.all(~over | (e_p <= kappa)), (e_p[over], kappa[over])
+    assert res["max_e_x"] <= TOL32
+    assert res["p99_e_p"] <= 1e-6
 
 
 @pytest.mark.parametrize("order", [1, 3])
