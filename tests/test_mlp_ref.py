@@ -124,3 +124,34 @@ def test_features_on_a_uniform_field():
     assert not f[1].any()        # xi < 1/2
     assert not f[2].any()        # not live
     assert not f[3].any()        # xi >= ncells - 1
+
+
+def test_features_on_fields_linear_in_x():
+    """Levels linear in x with different slopes for E and B and for the two
+    levels: the tent gather reproduces a linear field exactly, so every
+    feature has a closed form.  E nodes sit at x_origin + (i + 1/2) dx and B
+    nodes at x_origin + i dx (the Yee stagger of Sec. III), level n-1 is the
+    first of each pair and n-2 the second; taking E on B's nodes, swapping
+    the levels or the fields each changes a value by a slope times dx / 2 or
+    flips a sign, which this test sees."""
+    nc, x0, dx, dt = 40, -3.0, 0.25, 0.2
+    iE = x0 + (np.arange(nc) + 0.5) * dx          # E node positions
+    iB = x0 + np.arange(nc) * dx                  # B node positions
+    sE1, cE1, sE2, cE2 = 1.5, 0.25, -0.5, 2.0
+    sB1, cB1, sB2, cB2 = -2.0, 1.0, 0.75, -0.5
+    E = (sE1 * iE + cE1, sE2 * iE + cE2)
+    B = (sB1 * iB + cB1, sB2 * iB + cB2)
+    x = np.array([-2.5, -1.1, 0.3, 2.9, 5.6])
+    px = np.array([0.5, -1.0, 3.0, 0.0, 10.0])
+    py = np.array([1.0, 2.0, -4.0, 0.0, 0.5])
+    pz = np.array([0.0, 0.5, 0.0, 0.0, 2.0])
+    live = np.ones(len(x), dtype=bool)
+    f = R.features(x, px, py, pz, live, E, B, x_origin=x0, dx=dx, dt=dt, a0=7.0, ncells=nc)
+    e1, e2 = sE1 * x + cE1, sE2 * x + cE2
+    b1, b2 = sB1 * x + cB1, sB2 * x + cB2
+    want = np.stack([np.abs(e1), np.abs(b1), (e1 - e2) / dt, (b1 - b2) / dt,
+                     np.sqrt(1 + px ** 2 + py ** 2 + pz ** 2), px, np.hypot(py, pz),
+                     np.full(len(x), math.log(7.0))], axis=1)
+    assert np.allclose(f, want, rtol=1e-13, atol=1e-13)
+    # a gather that took E's nodes for B's would read E at x + dx / 2
+    assert np.all(np.abs(np.abs(sE1 * (x + dx / 2) + cE1) - f[:, 0]) > 0.1 * dx)
