@@ -216,6 +216,20 @@ pic_status pic_diag(pic_ctx *ctx, pic_mem mem, double *gamma, double *px,
                     double *py, double *pz, double *x, int8_t *k_last,
                     uint8_t *status, pic_counters *cnt);
 
+/* pic_diag with host outputs that allocates nothing, for callers that
+ * cannot allocate device memory (serving loops, code that must not call
+ * hipMalloc).  The same values as pic_diag(ctx, PIC_MEM_HOST, ...) (host
+ * arrays, any pointer may be NULL), staged through a fixed array of the
+ * library's own in each GPU's memory (about 64 MiB, held from the load of the
+ * library until the process ends) instead of a per-call allocation.
+ * PIC_E_ARG if the context holds more than PIC_DIAG_NOALLOC_MAX_NP
+ * particles.  Synchronises the stream.  All calls on one GPU share that
+ * array: calls that overlap on one GPU (other threads, other streams) race,
+ * and callers must serialise them. */
+#define PIC_DIAG_NOALLOC_MAX_NP 1572864
+pic_status pic_diag_noalloc(pic_ctx *ctx, double *gamma, double *px, double *py, double *pz,
+                            double *x, int8_t *k_last, uint8_t *status, pic_counters *cnt);
+
 /* Reset the counters to zero (asynchronous). */
 pic_status pic_counters_reset(pic_ctx *ctx);
 

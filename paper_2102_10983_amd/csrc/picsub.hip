@@ -60,6 +60,36 @@ struct RunHost {
     int64_t n_stop = INT64_MAX;  // device-driven stop level
 };
 
+// Staging area of pic_diag_noalloc: a layout of [counter sums: NCNT words,
+// padded to 256 B][gamma, px, py, pz, x: PIC_DIAG_NOALLOC_MAX_NP doubles
+// each][k_last: int8][status: uint8].  Every GPU the library runs on holds
+// its own copy from the load of the code object until the process ends.
+// Host code never passes the array's name to a kernel or a copy (on the host
+// it only names the symbol): it uses the device address that
+// hipGetSymbolAddress returned for the current device.
+constexpr size_t NOALLOC_HEAD = 256;
+constexpr size_t NOALLOC_BYTES = NOALLOC_HEAD + size_t(PIC_DIAG_NOALLOC_MAX_NP) * (5 * 8 + 2);
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+hipError_t g_scratch_err[NOALLOC_MAX_DEVICES] = {};
+
+// Once per device, with that device current (pic_batch_create's device):
+// the device address of `scratch`.  A failure is kept and reported by
+// pic_diag_noalloc; the other entry points do not need the array.
+void scratch_setup(int device)
+{
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES) return;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device] || g_scratch_err[device] != hipSuccess) return;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e == hipSuccess && p) g_scratch_ptr[device] = static_cast<unsigned char *>(p);
+    else g_scratch_err[device] = e != hipSuccess ? e : hipErrorInvalidSymbol;
+}
+
 struct pic_ctx {
     std::vector<RunHost> runs;
     int32_t nruns = 0;
@@ -401,30 +431,40 @@ void mirror_advance(pic_ctx *ctx, int64_t steps, int32_t S)
     }
 }
 
+// pic_counters from the counter words summed over slots (and runs): steps
+// per k, clamps, lost; sub-steps are 4^k per step, N* the sub-steps of k > 0
+// (Sec. VII).
+void counters_from_sums(const uint64_t (&sum)[NCNT], uint64_t rebins, pic_counters *cnt)
+{
+    std::memset(cnt, 0, sizeof *cnt);
+    for (int k = 0; k < PIC_KHIST; ++k) {
+        cnt->steps_by_k[k] = sum[k];
+        const uint64_t sub = sum[k] << (2 * k);
+        cnt->sub_steps_by_k[k] = sub;
+        cnt->steps += sum[k];
+        cnt->sub_steps += sub;
+        if (k > 0) cnt->n_star += sub;
+    }
+    cnt->clamps = sum[CNT_CLAMPS];
+    cnt->lost = sum[CNT_LOST];
+    cnt->rebins = rebins;
+}
+
 pic_status read_counters(pic_ctx *ctx, int32_t run, pic_counters *cnt)
 {
     std::vector<uint64_t> h(cnt_words(ctx));
     HIP_TRY(ctx, hipMemcpyAsync(h.data(), ctx->cnt, h.size() * sizeof(uint64_t),
                                 hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-    std::memset(cnt, 0, sizeof *cnt);
+    uint64_t sum[NCNT] = {0};
     for (int r = 0; r < ctx->nruns; ++r) {
         if (run >= 0 && r != run) continue;
         for (int b = 0; b < NSLOT; ++b) {
             const uint64_t *v = h.data() + (size_t(r) * NSLOT + b) * NCNT;
-            for (int k = 0; k < PIC_KHIST; ++k) cnt->steps_by_k[k] += v[k];
-            cnt->clamps += v[CNT_CLAMPS];
-            cnt->lost += v[CNT_LOST];
+            for (int j = 0; j < NCNT; ++j) sum[j] += v[j];
         }
     }
-    for (int k = 0; k < PIC_KHIST; ++k) {
-        const uint64_t sub = cnt->steps_by_k[k] << (2 * k);
-        cnt->sub_steps_by_k[k] = sub;
-        cnt->steps += cnt->steps_by_k[k];
-        cnt->sub_steps += sub;
-        if (k > 0) cnt->n_star += sub;
-    }
-    cnt->rebins = ctx->rebins;
+    counters_from_sums(sum, ctx->rebins, cnt);
     return PIC_OK;
 }
 
@@ -477,6 +517,7 @@ pic_status pic_batch_create(const pic_params *per_run, const int64_t *np, int32_
     hipError_t e = hipGetDevice(&ctx->device);
     if (e != hipSuccess) return fail(ctx, PIC_E_DEVICE, "hipGetDevice: %s", hipGetErrorString(e));
     (void)hipDeviceGetAttribute(&ctx->ncu, hipDeviceAttributeMultiprocessorCount, ctx->device);
+    scratch_setup(ctx->device);
     ctx->runs.resize(size_t(nruns));
     int64_t caller = 0, slot = 0;
     for (int r = 0; r < nruns; ++r) {
@@ -999,6 +1040,67 @@ pic_status pic_diag(pic_ctx *ctx, pic_mem mem, double *gamma, double *px, double
         }
     }
     if (cnt) return read_counters(ctx, -1, cnt);
+    return PIC_OK;
+}
+
+pic_status pic_diag_noalloc(pic_ctx *ctx, double *gamma, double *px, double *py, double *pz,
+                            double *x, int8_t *k_last, uint8_t *status, pic_counters *cnt)
+{
+    CTX_CHECK(ctx);
+    const int64_t np = ctx->np;
+    if (np > PIC_DIAG_NOALLOC_MAX_NP)
+        return fail(ctx, PIC_E_ARG, "pic_diag_noalloc: %lld particles exceed its maximum of %d",
+                    (long long)np, PIC_DIAG_NOALLOC_MAX_NP);
+    unsigned char *base = nullptr;
+    if (ctx->device >= 0 && ctx->device < NOALLOC_MAX_DEVICES) {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        base = g_scratch_ptr[ctx->device];
+        if (!base)
+            return fail(ctx, PIC_E_DEVICE, "pic_diag_noalloc: no address of its staging array "
+                        "on device %d: %s", ctx->device,
+                        hipGetErrorString(g_scratch_err[ctx->device]));
+    } else {
+        return fail(ctx, PIC_E_DEVICE, "pic_diag_noalloc: device %d out of range", ctx->device);
+    }
+    const size_t n = size_t(np);
+    const bool any = gamma || px || py || pz || x || k_last || status;
+    if (any && np > 0 && !ctx->have_particles) return fail(ctx, PIC_E_STATE, "particles not loaded");
+    uint64_t *dsum = reinterpret_cast<uint64_t *>(base);
+    double *d = reinterpret_cast<double *>(base + NOALLOC_HEAD);
+    int8_t *dk = reinterpret_cast<int8_t *>(d + 5 * n);
+    uint8_t *ds = reinterpret_cast<uint8_t *>(dk + n);
+    if (any && np > 0) {
+        diag_kernel<<<grid_for(ctx->slots, 256, 8192), 256, 0, ctx->stream>>>(
+            ctx->perm, ctx->slots, ctx->x, ctx->px, ctx->py, ctx->pz, ctx->kold, ctx->status,
+            gamma ? d : nullptr, px ? d + n : nullptr, py ? d + 2 * n : nullptr,
+            pz ? d + 3 * n : nullptr, x ? d + 4 * n : nullptr, k_last ? dk : nullptr,
+            status ? ds : nullptr);
+        LAUNCH_CHECK(ctx);
+    }
+    if (cnt) {
+        counter_sum_kernel<<<1, 256, 0, ctx->stream>>>(ctx->cnt, int64_t(ctx->nruns) * NSLOT, dsum);
+        LAUNCH_CHECK(ctx);
+    }
+    uint64_t sum[NCNT] = {0};
+    hipError_t e = hipSuccess;
+    if (any && np > 0) {
+        double *outs[5] = {gamma, px, py, pz, x};
+        for (int a = 0; a < 5 && e == hipSuccess; ++a)
+            if (outs[a])
+                e = hipMemcpyAsync(outs[a], d + a * n, n * sizeof(double), hipMemcpyDeviceToHost,
+                                   ctx->stream);
+        if (e == hipSuccess && k_last)
+            e = hipMemcpyAsync(k_last, dk, n, hipMemcpyDeviceToHost, ctx->stream);
+        if (e == hipSuccess && status)
+            e = hipMemcpyAsync(status, ds, n, hipMemcpyDeviceToHost, ctx->stream);
+    }
+    if (e == hipSuccess && cnt)
+        e = hipMemcpyAsync(sum, dsum, sizeof sum, hipMemcpyDeviceToHost, ctx->stream);
+    const hipError_t e2 = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess || e2 != hipSuccess)
+        return fail(ctx, PIC_E_DEVICE, "pic_diag_noalloc: %s",
+                    hipGetErrorString(e != hipSuccess ? e : e2));
+    if (cnt) counters_from_sums(sum, ctx->rebins, cnt);
     return PIC_OK;
 }
 

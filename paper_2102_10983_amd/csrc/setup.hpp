@@ -269,6 +269,28 @@ __global__ void diag_kernel(const int32_t *__restrict__ perm, int64_t slots,
     }
 }
 
+// Sum of the counter words over `rows` slots (all runs): out[j] = sum_r
+// cnt[r][j], one workgroup of 256 threads.  Every word of out is written.
+__global__ void __launch_bounds__(256) counter_sum_kernel(const uint64_t *__restrict__ cnt,
+                                                          int64_t rows, uint64_t *__restrict__ out)
+{
+    __shared__ uint64_t part[256][NCNT];
+    uint64_t acc[NCNT];
+#pragma unroll
+    for (int j = 0; j < NCNT; ++j) acc[j] = 0;
+    for (int64_t r = threadIdx.x; r < rows; r += 256)
+#pragma unroll
+        for (int j = 0; j < NCNT; ++j) acc[j] += cnt[r * NCNT + j];
+#pragma unroll
+    for (int j = 0; j < NCNT; ++j) part[threadIdx.x][j] = acc[j];
+    __syncthreads();
+    if (threadIdx.x < NCNT) {
+        uint64_t s = 0;
+        for (int t = 0; t < 256; ++t) s += part[t][threadIdx.x];
+        out[threadIdx.x] = s;
+    }
+}
+
 // Trajectory diagnostics: R0 = gamma - p_x of the stored momentum of every
 // slot; running maximum, work and largest step energy error reset to zero.
 __global__ void diag_init_kernel(int64_t slots, const double *__restrict__ px,

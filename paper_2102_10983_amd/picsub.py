@@ -26,7 +26,8 @@ MEM_HOST, MEM_DEVICE = 0, 1
 # every symbol the header declares
 EXPORTS = ("pic_create", "pic_destroy", "pic_last_error", "pic_particles_set",
            "pic_fields_load", "pic_fields_load_lattice", "pic_push_subcycled",
-           "pic_ktrace_set", "pic_diag", "pic_counters_reset", "pic_batch_create",
+           "pic_ktrace_set", "pic_diag", "pic_diag_noalloc", "pic_counters_reset",
+           "pic_batch_create",
            "pic_fields_load_r", "pic_fields_load_lattice_r", "pic_source_set", "pic_advance",
            "pic_run_level", "pic_graph_capture", "pic_graph_launch", "pic_graph_release",
            "pic_run_counters", "pic_tune_set", "pic_tune_get", "pic_autotune",
@@ -103,6 +104,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "pic_push_subcycled": ([vp, i64, i32], C.c_int),
         "pic_ktrace_set": ([vp, vp, i64, i32, i64, i64], C.c_int),
         "pic_diag": ([vp, C.c_int, vp, vp, vp, vp, vp, vp, vp, C.POINTER(Counters)], C.c_int),
+        "pic_diag_noalloc": ([vp, vp, vp, vp, vp, vp, vp, vp, C.POINTER(Counters)], C.c_int),
         "pic_counters_reset": ([vp], C.c_int),
         "pic_batch_create": ([vp, vp, i32, vp, C.POINTER(vp)], C.c_int),
         "pic_fields_load_r": ([vp, i32, i64, C.c_int, vp, vp], C.c_int),
@@ -494,6 +496,25 @@ class Pusher:
             self._ctx, MEM_HOST, *[out[k].ctypes.data for k in ("gamma", "px", "py", "pz", "x")],
             out["k_last"].ctypes.data, out["status"].ctypes.data, C.byref(c)))
         out["counters"] = c.as_dict()
+        return out
+
+    def diag_noalloc(self, keys=("gamma", "px", "py", "pz", "x", "k_last", "status"),
+                     counters: bool = True) -> dict:
+        """pic_diag_noalloc: the host copies of diag() (only `keys`), staged
+        through the library's fixed per-GPU array instead of an allocation."""
+        n = self.num
+        out = {k: np.empty(n) for k in ("gamma", "px", "py", "pz", "x") if k in keys}
+        if "k_last" in keys:
+            out["k_last"] = np.empty(n, dtype=np.int8)
+        if "status" in keys:
+            out["status"] = np.empty(n, dtype=np.uint8)
+        c = Counters()
+        ptrs = [out[k].ctypes.data if k in out else None
+                for k in ("gamma", "px", "py", "pz", "x", "k_last", "status")]
+        self._check(self._lib.pic_diag_noalloc(self._ctx, *ptrs,
+                                               C.byref(c) if counters else None))
+        if counters:
+            out["counters"] = c.as_dict()
         return out
 
     def diag_device(self, out: dict):
