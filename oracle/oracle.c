@@ -188,6 +188,10 @@ static int one_step(const orc_params *prm, const orc_fields *f, int64_t n,
     double Ep, Bp;
     int rc;
 
+    /* a state that is not finite is frozen and flagged like a particle that
+     * left the grid (the paper's electrons always have a finite state; the
+     * rule only keeps bad input from spreading) */
+    if (!isfinite(*x) || !isfinite(*px) || !isfinite(*py) || !isfinite(*pz)) return 1;
     /* decision: Psi over a full dt with B at (x_n, s = 1/2) and gamma of
      * the stored momentum (Sec. IV) */
     double xi = grid_coord(prm, *x);

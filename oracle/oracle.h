@@ -49,7 +49,8 @@ extern "C" {
 
 /* status flags of a particle (same meaning as in the product library) */
 #define ORC_LIVE 0
-#define ORC_LOST 1 /* left the range where both tent nodes exist */
+#define ORC_LOST 1 /* left the range where both tent nodes exist, or its
+                     state (x, p) is not finite at the start of a step */
 
 typedef struct {
     int32_t ncells;   /* number of E and of B nodes on the 1D grid */

@@ -360,6 +360,34 @@ def test_lost_particle_is_frozen_and_counted(orc):
     assert 0.0 <= st.x[0] < 0.5 * dx + 1.0
 
 
+def test_non_finite_particle_is_frozen_and_counted(orc):
+    """A particle whose x or p is NaN or infinite is flagged lost at its
+    first step, counted once, never advanced (its values come back as
+    given), and the others advance exactly as they would without it."""
+    ncells, dx, dt = 32, 1.0, 0.5
+    E, B = _uniform_levels(3, ncells, 40, lambda t: 0 * t + 1.0, lambda t: 0 * t + 0.5, dt)
+    fs = orc.FieldSource(E=E, B=B, lev0=0)
+    prm = orc.make_params(ncells, 3, dx, dt, 0.01)
+    nan, inf = float("nan"), float("inf")
+    x = np.array([8.0, nan, 9.0, 10.0, 11.0, inf])
+    px = np.array([0.0, 0.0, inf, 0.0, 0.0, 0.0])
+    py = np.array([0.0, 0.0, 0.0, 0.0, -inf, 0.0])
+    pz = np.array([0.0, 0.0, 0.0, nan, 0.0, 0.0])
+    st = orc.State(x, px, py, pz)
+    cnt = orc.Counters()
+    kt, _ = orc.push(prm, fs, st, 3, 5, counters=cnt, trace=True)
+    bad = np.array([False, True, True, True, True, True])
+    assert np.array_equal(st.status, bad.astype(np.uint8)) and cnt.lost == 5
+    assert np.all(kt[:, bad] == -1) and np.all(kt[:, 0] >= 0)
+    for a, b in ((st.x, x), (st.px, px), (st.py, py), (st.pz, pz)):
+        assert np.array_equal(a[bad], b[bad], equal_nan=True)
+    ref = orc.State(x[:1], px[:1], py[:1], pz[:1])
+    cref = orc.Counters()
+    orc.push(prm, fs, ref, 3, 5, counters=cref)
+    assert (st.x[0], st.px[0], st.py[0]) == (ref.x[0], ref.px[0], ref.py[0])
+    assert cnt.steps == cref.steps == 5 and cnt.sub_steps == cref.sub_steps
+
+
 # ---------------------------------------------------------------------------
 # The whole integrator against the plane-wave solution (Sec. II, appendix)
 # ---------------------------------------------------------------------------
