@@ -56,7 +56,9 @@ typedef enum {
     PIC_E_DEVICE = 2,  /* a HIP call failed */
     PIC_E_NOMEM = 3,   /* device or host allocation failed */
     PIC_E_LEVEL = 4,   /* a field level the push needs is not in the ring */
-    PIC_E_STATE = 5    /* call out of order (e.g. push before particles) */
+    PIC_E_STATE = 5,   /* call out of order (e.g. push before particles) */
+    PIC_E_NUMERIC = 6  /* strict mode (pic_strict_set): particle or field input
+                          holds a value that is not finite */
 } pic_status;
 
 typedef enum { PIC_MEM_HOST = 0, PIC_MEM_DEVICE = 1 } pic_mem;
@@ -93,16 +95,20 @@ typedef enum {
 } pic_binning;
 
 #define PIC_PARTICLE_LIVE 0u
-#define PIC_PARTICLE_LOST 1u
+#define PIC_PARTICLE_LOST 1u   /* left the grid (its tent nodes are not all on
+                                  it), or its x or p was not finite at the start
+                                  of a step; frozen from then on */
 
 #define PIC_KHIST 16
-#define PIC_K_MAX_LIMIT 8
+#define PIC_K_MAX_LIMIT 12
 
 typedef struct {
     int32_t ncells;      /* nodes per field, >= 2 */
     int32_t order;       /* temporal interpolation order p: 1, 3 or 5 */
     int32_t ring_depth;  /* stored levels, >= order + 1 */
-    int32_t k_max;       /* cap of k, 0..PIC_K_MAX_LIMIT */
+    int32_t k_max;       /* cap of k, 0..PIC_K_MAX_LIMIT (the weight table holds
+                            (4^(k_max+1) - 1) / 3 entries of 2 (order + 1)
+                            doubles: 1.4 GB at k_max = 12, order 3) */
     int32_t precision;   /* pic_precision */
     int32_t binning;     /* pic_binning */
     double x_origin;     /* x of B node 0 */
@@ -121,7 +127,12 @@ typedef struct {
     uint64_t steps_by_k[PIC_KHIST];
     uint64_t sub_steps_by_k[PIC_KHIST];
     uint64_t rebins;      /* group re-orderings made by an attached predictor
-                             (pic_predictor_set), whole context */
+                             (pic_predictor_set), whole context.  There is no
+                             count of mispredicted steps: the predictor ranks
+                             groups by their expected load over the coming
+                             launch instead of guessing each next step's k, so
+                             no per-step prediction exists to be wrong; a poor
+                             ranking shows as time only */
 } pic_counters;
 
 typedef struct pic_ctx pic_ctx;
@@ -142,12 +153,16 @@ pic_status pic_destroy(pic_ctx *ctx);
  * call on ctx. */
 const char *pic_last_error(const pic_ctx *ctx);
 
-/* Load the particle state: x, px, py, pz (np doubles each, the time
- * convention above; may be NULL when np == 0) and k_old (np int8; NULL
- * means -1 for all).  Resets
- * the status flags and the counters.  Particles are reordered internally
- * by position (cell index); every per-particle output is returned in the
- * caller's original order. */
+/* Load the particle state: x, px, py, pz (np doubles each; may be NULL when
+ * np == 0) and k_old (np int8; NULL means -1 for all), in the time
+ * convention of Algorithm 1 (Sec. IV): x at t = n dt and p half the previous
+ * sub-step behind, at n dt - dt*_old / 2 with dt*_old = dt / 4^k_old (the
+ * leapfrog stagger of the Boris scheme, Sec. III).  Resets the status flags
+ * and the counters.  Particles are reordered internally by position (cell
+ * index); every per-particle output is returned in the caller's original
+ * order.  A particle whose x or p is not finite is flagged
+ * PIC_PARTICLE_LOST at its first step and never moved; in strict mode the
+ * call returns PIC_E_NUMERIC instead and loads nothing. */
 pic_status pic_particles_set(pic_ctx *ctx, pic_mem mem, const double *x,
                              const double *px, const double *py,
                              const double *pz, const int8_t *k_old);
@@ -208,13 +223,29 @@ pic_status pic_push_subcycled(pic_ctx *ctx, int64_t n, int32_t S);
 pic_status pic_ktrace_set(pic_ctx *ctx, int8_t *buf, int64_t n_first,
                           int32_t steps, int64_t first, int64_t count);
 
-/* Read the state: gamma = sqrt(1 + |p|^2) of the stored momentum, p, x,
- * the last k, the status flags (np entries each, caller order; any
- * pointer may be NULL) and the counters (may be NULL).  With
- * PIC_MEM_HOST the call synchronises the stream. */
+/* Read the state: the Lorentz factor gamma = sqrt(1 + |p|^2) of the stored
+ * momentum (Sec. III, Eq. (gamma); with p_x it gives the dephasing
+ * invariant R = gamma - p_x of Sec. V, Eq. (R error)), p, x, the last k, the
+ * status flags (np entries each, caller order; any pointer may be NULL) and
+ * the counters (may be NULL): N and N* of Sec. VII (delta_steps), the steps
+ * and sub-steps of each k, clamps and lost particles.  With PIC_MEM_HOST the
+ * call synchronises the stream. */
 pic_status pic_diag(pic_ctx *ctx, pic_mem mem, double *gamma, double *px,
                     double *py, double *pz, double *x, int8_t *k_last,
                     uint8_t *status, pic_counters *cnt);
+
+/* pic_diag for one run of a batch: np[run] entries per output, in the
+ * caller order of that run's particles, and the counters of that run. */
+pic_status pic_diag_r(pic_ctx *ctx, int32_t run, pic_mem mem, double *gamma,
+                      double *px, double *py, double *pz, double *x,
+                      int8_t *k_last, uint8_t *status, pic_counters *cnt);
+
+/* Strict mode (on != 0): pic_particles_set, pic_fields_load*,
+ * pic_fields_yee* and pic_source_set check their particle arrays, levels or
+ * phase table and return PIC_E_NUMERIC, loading nothing, if a value is not
+ * finite (each check reads the whole input: a synchronising pass).  Off (the
+ * default): non-finite particles are frozen and flagged as above. */
+pic_status pic_strict_set(pic_ctx *ctx, int32_t on);
 
 /* pic_diag with host outputs that allocates nothing, for callers that
  * cannot allocate device memory (serving loops, code that must not call

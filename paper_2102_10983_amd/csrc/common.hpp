@@ -261,6 +261,14 @@ __device__ __forceinline__ void set_prio(int p)
     }
 }
 
+// A particle whose momentum is not finite is frozen and flagged lost at its
+// first step, as one whose x is not finite fails the grid test; its stored
+// state is left as it was.
+__device__ __forceinline__ bool nonfinite_p(double px, double py, double pz)
+{
+    return !(__builtin_isfinite(px) & __builtin_isfinite(py) & __builtin_isfinite(pz));
+}
+
 // Steps this run takes in a launch of S steps starting at n0.
 __device__ __forceinline__ int run_steps(const PushArgs &a, const RunDesc &R, int64_t n0)
 {

@@ -113,6 +113,9 @@ struct pic_ctx {
     int32_t ngroups = 0;
     double *wtab = nullptr;
     uint64_t *cnt = nullptr;
+    // strict mode: non-finite particle or field input is refused (PIC_E_NUMERIC)
+    bool strict = false;
+    int32_t *d_flag = nullptr;
     // attached load predictor (pic_predictor_set)
     uint16_t *pred_w = nullptr;
     float *pred_norm = nullptr, *pred_feat = nullptr, *pred_score = nullptr;
@@ -190,7 +193,7 @@ void free_all(pic_ctx *c)
     void *ptrs[] = {c->x, c->px, c->py, c->pz, c->kold, c->status, c->perm, c->key,
                     c->d_runs, c->group_run, c->group_order, c->group_prio, c->wtab, c->cnt,
                     c->r0, c->rmax, c->work, c->werr, c->pred_w, c->pred_norm, c->pred_feat,
-                    c->pred_score};
+                    c->pred_score, c->d_flag};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (RunHost &r : c->runs) {
@@ -210,6 +213,7 @@ void free_all(pic_ctx *c)
     c->pred_w = nullptr;
     c->pred_norm = c->pred_feat = c->pred_score = nullptr;
     c->pred_every = 0;
+    c->d_flag = nullptr;
 }
 
 pic_status check_params(pic_ctx *ctx, const pic_params *p, int64_t np, int r)
@@ -252,6 +256,26 @@ pic_status dev_alloc(pic_ctx *ctx, T **p, size_t n)
         return fail(ctx, PIC_E_NOMEM, "hipMalloc(%zu bytes) failed: %s", n * sizeof(T),
                     hipGetErrorString(e));
     }
+    return PIC_OK;
+}
+
+// Strict mode: PIC_E_NUMERIC if any of a[0 .. n) (host or device memory)
+// is not finite.  Synchronous.
+pic_status check_finite(pic_ctx *ctx, pic_mem mem, const double *a, int64_t n, const char *what)
+{
+    if (!ctx->strict || n <= 0 || !a) return PIC_OK;
+    int32_t bad = 0;
+    if (mem == PIC_MEM_HOST) {
+        for (int64_t i = 0; i < n && !bad; ++i) bad = !std::isfinite(a[i]);
+    } else {
+        HIP_TRY(ctx, hipMemsetAsync(ctx->d_flag, 0, sizeof(int32_t), ctx->stream));
+        nonfinite_kernel<<<grid_for(n, 256, 4096), 256, 0, ctx->stream>>>(a, n, ctx->d_flag);
+        LAUNCH_CHECK(ctx);
+        HIP_TRY(ctx, hipMemcpyAsync(&bad, ctx->d_flag, sizeof bad, hipMemcpyDeviceToHost,
+                                    ctx->stream));
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    if (bad) return fail(ctx, PIC_E_NUMERIC, "%s holds a value that is not finite", what);
     return PIC_OK;
 }
 
@@ -548,7 +572,8 @@ pic_status pic_batch_create(const pic_params *per_run, const int64_t *np, int32_
         (st = dev_alloc(ctx, &ctx->group_order, size_t(ctx->ngroups))) ||
         (st = dev_alloc(ctx, &ctx->group_prio, size_t(ctx->ngroups))) ||
         (st = dev_alloc(ctx, &ctx->wtab, size_t(wtab_entries(ctx->kmax_all)) * 2 * (ctx->order + 1))) ||
-        (st = dev_alloc(ctx, &ctx->cnt, cnt_words(ctx)))) {
+        (st = dev_alloc(ctx, &ctx->cnt, cnt_words(ctx))) ||
+        (st = dev_alloc(ctx, &ctx->d_flag, 1))) {
         free_all(ctx);
         return st;
     }
@@ -616,6 +641,14 @@ pic_status load_particles(pic_ctx *ctx, pic_mem mem, const double *x, const doub
     const int64_t np = ctx->np;
     if (np > 0 && (!x || !px || !py || !pz)) return fail(ctx, PIC_E_ARG, "null particle array");
     if (mem != PIC_MEM_HOST && mem != PIC_MEM_DEVICE) return fail(ctx, PIC_E_ARG, "bad pic_mem");
+    {
+        const double *arr[4] = {x, px, py, pz};
+        const char *name[4] = {"x", "px", "py", "pz"};
+        for (int a = 0; a < 4; ++a) {
+            pic_status s = check_finite(ctx, mem, arr[a], np, name[a]);
+            if (s) return s;
+        }
+    }
     const size_t n = size_t(np);
     const double *dx_ = x, *dpx = px, *dpy = py, *dpz = pz;
     const int8_t *dk = k_old;
@@ -732,6 +765,10 @@ pic_status pic_fields_load_r(pic_ctx *ctx, int32_t run, int64_t n, pic_mem mem, 
     if (!Ey || !Bz) return fail(ctx, PIC_E_ARG, "null field array");
     if (mem != PIC_MEM_HOST && mem != PIC_MEM_DEVICE) return fail(ctx, PIC_E_ARG, "bad pic_mem");
     RunHost &R = ctx->runs[size_t(run)];
+    pic_status fs;
+    if ((fs = check_finite(ctx, mem, Ey, R.prm.ncells, "Ey")) ||
+        (fs = check_finite(ctx, mem, Bz, R.prm.ncells, "Bz")))
+        return fs;
     const int64_t slot = mod_floor(n, R.prm.ring_depth);
     const size_t bytes = size_t(R.prm.ncells) * sizeof(double);
     const hipMemcpyKind kind = mem == PIC_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
@@ -757,6 +794,7 @@ pic_status pic_fields_load_lattice_r(pic_ctx *ctx, int32_t run, int64_t n_first,
     RunHost &R = ctx->runs[size_t(run)];
     const int D = R.prm.ring_depth;
     if (count < 0 || count > D) return fail(ctx, PIC_E_ARG, "count must be in [0, ring_depth]");
+    if (pic_status fs = check_finite(ctx, PIC_MEM_DEVICE, table, M, "the phase table")) return fs;
     if (count == 0) return PIC_OK;
     const int64_t work = int64_t(count) * R.prm.ncells;
     lattice_kernel<<<grid_for(work, 256, 16384), 256, 0, ctx->stream>>>(
@@ -782,6 +820,7 @@ pic_status pic_fields_yee_r(pic_ctx *ctx, int32_t run, int64_t n_first, int32_t 
     RunHost &R = ctx->runs[size_t(run)];
     const int D = R.prm.ring_depth;
     const int32_t N = R.prm.ncells;
+    if (pic_status fs = check_finite(ctx, PIC_MEM_DEVICE, table, M, "the phase table")) return fs;
     if (count < 0 || count > D - 1) return fail(ctx, PIC_E_ARG, "count must be in [0, ring_depth - 1]");
     if (N < 2) return fail(ctx, PIC_E_ARG, "the Yee solver needs two or more cells");
     if (count == 0) return PIC_OK;
@@ -841,6 +880,7 @@ pic_status pic_source_set(pic_ctx *ctx, int32_t run, int64_t n_start, int64_t n_
     if (run < 0 || run >= ctx->nruns) return fail(ctx, PIC_E_ARG, "bad run %d", run);
     if (!table || M <= 0) return fail(ctx, PIC_E_ARG, "bad table");
     if (n_stop < n_start) return fail(ctx, PIC_E_ARG, "n_stop before n_start");
+    if (pic_status fs = check_finite(ctx, PIC_MEM_DEVICE, table, M, "the phase table")) return fs;
     RunHost &R = ctx->runs[size_t(run)];
     R.driven = true;
     R.n_stop = n_stop;
@@ -975,6 +1015,13 @@ pic_status pic_push_subcycled(pic_ctx *ctx, int64_t n, int32_t S)
     return launch_push(ctx, n, S, ctx->stream);
 }
 
+pic_status pic_strict_set(pic_ctx *ctx, int32_t on)
+{
+    CTX_CHECK(ctx);
+    ctx->strict = on != 0;
+    return PIC_OK;
+}
+
 pic_status pic_counters_reset(pic_ctx *ctx)
 {
     CTX_CHECK(ctx);
@@ -990,56 +1037,74 @@ pic_status pic_run_counters(pic_ctx *ctx, int32_t run, pic_counters *cnt)
     return read_counters(ctx, run, cnt);
 }
 
+// pic_diag's per-particle outputs for caller indices u_lo .. u_lo + u_n - 1.
+pic_status diag_range(pic_ctx *ctx, pic_mem mem, int64_t u_lo, int64_t u_n, double *gamma,
+                      double *px, double *py, double *pz, double *x, int8_t *k_last,
+                      uint8_t *status)
+{
+    if (mem != PIC_MEM_HOST && mem != PIC_MEM_DEVICE) return fail(ctx, PIC_E_ARG, "bad pic_mem");
+    const size_t n = size_t(u_n);
+    const bool any = gamma || px || py || pz || x || k_last || status;
+    if (!any || u_n <= 0) return PIC_OK;
+    if (!ctx->have_particles) return fail(ctx, PIC_E_STATE, "particles not loaded");
+    const int grid = grid_for(ctx->slots, 256, 8192);
+    if (mem == PIC_MEM_DEVICE) {
+        diag_kernel<<<grid, 256, 0, ctx->stream>>>(ctx->perm, ctx->slots, ctx->x, ctx->px, ctx->py,
+                                                   ctx->pz, ctx->kold, ctx->status, u_lo, u_n,
+                                                   gamma, px, py, pz, x, k_last, status);
+        LAUNCH_CHECK(ctx);
+        return PIC_OK;
+    }
+    double *d = nullptr;
+    int8_t *dk = nullptr;
+    uint8_t *ds = nullptr;
+    pic_status st = dev_alloc(ctx, &d, 5 * n);
+    if (st) return st;
+    if ((st = dev_alloc(ctx, &dk, n)) || (st = dev_alloc(ctx, &ds, n))) {
+        (void)hipFree(d);
+        if (dk) (void)hipFree(dk);
+        return st;
+    }
+    diag_kernel<<<grid, 256, 0, ctx->stream>>>(ctx->perm, ctx->slots, ctx->x, ctx->px, ctx->py,
+                                               ctx->pz, ctx->kold, ctx->status, u_lo, u_n, d,
+                                               d + n, d + 2 * n, d + 3 * n, d + 4 * n, dk, ds);
+    hipError_t e = hipGetLastError();
+    double *outs[5] = {gamma, px, py, pz, x};
+    for (int a = 0; a < 5 && e == hipSuccess; ++a)
+        if (outs[a])
+            e = hipMemcpyAsync(outs[a], d + a * n, n * sizeof(double), hipMemcpyDeviceToHost,
+                               ctx->stream);
+    if (e == hipSuccess && k_last) e = hipMemcpyAsync(k_last, dk, n, hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess && status) e = hipMemcpyAsync(status, ds, n, hipMemcpyDeviceToHost, ctx->stream);
+    hipError_t e2 = hipStreamSynchronize(ctx->stream);
+    (void)hipFree(d);
+    (void)hipFree(dk);
+    (void)hipFree(ds);
+    if (e != hipSuccess || e2 != hipSuccess)
+        return fail(ctx, PIC_E_DEVICE, "diag copy: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+    return PIC_OK;
+}
+
 pic_status pic_diag(pic_ctx *ctx, pic_mem mem, double *gamma, double *px, double *py, double *pz,
                     double *x, int8_t *k_last, uint8_t *status, pic_counters *cnt)
 {
     CTX_CHECK(ctx);
-    if (mem != PIC_MEM_HOST && mem != PIC_MEM_DEVICE) return fail(ctx, PIC_E_ARG, "bad pic_mem");
-    const int64_t np = ctx->np;
-    const size_t n = size_t(np);
-    const bool any = gamma || px || py || pz || x || k_last || status;
-    if (any && np > 0) {
-        if (!ctx->have_particles) return fail(ctx, PIC_E_STATE, "particles not loaded");
-        const int grid = grid_for(ctx->slots, 256, 8192);
-        if (mem == PIC_MEM_DEVICE) {
-            diag_kernel<<<grid, 256, 0, ctx->stream>>>(ctx->perm, ctx->slots, ctx->x, ctx->px,
-                                                       ctx->py, ctx->pz, ctx->kold, ctx->status,
-                                                       gamma, px, py, pz, x, k_last, status);
-            LAUNCH_CHECK(ctx);
-        } else {
-            double *d = nullptr;
-            int8_t *dk = nullptr;
-            uint8_t *ds = nullptr;
-            pic_status st = dev_alloc(ctx, &d, 5 * n);
-            if (st) return st;
-            if ((st = dev_alloc(ctx, &dk, n)) || (st = dev_alloc(ctx, &ds, n))) {
-                (void)hipFree(d);
-                if (dk) (void)hipFree(dk);
-                return st;
-            }
-            diag_kernel<<<grid, 256, 0, ctx->stream>>>(ctx->perm, ctx->slots, ctx->x, ctx->px,
-                                                       ctx->py, ctx->pz, ctx->kold, ctx->status, d,
-                                                       d + n, d + 2 * n, d + 3 * n, d + 4 * n, dk, ds);
-            hipError_t e = hipGetLastError();
-            double *outs[5] = {gamma, px, py, pz, x};
-            for (int a = 0; a < 5 && e == hipSuccess; ++a)
-                if (outs[a])
-                    e = hipMemcpyAsync(outs[a], d + a * n, n * sizeof(double),
-                                       hipMemcpyDeviceToHost, ctx->stream);
-            if (e == hipSuccess && k_last)
-                e = hipMemcpyAsync(k_last, dk, n, hipMemcpyDeviceToHost, ctx->stream);
-            if (e == hipSuccess && status)
-                e = hipMemcpyAsync(status, ds, n, hipMemcpyDeviceToHost, ctx->stream);
-            hipError_t e2 = hipStreamSynchronize(ctx->stream);
-            (void)hipFree(d);
-            (void)hipFree(dk);
-            (void)hipFree(ds);
-            if (e != hipSuccess || e2 != hipSuccess)
-                return fail(ctx, PIC_E_DEVICE, "diag copy: %s",
-                            hipGetErrorString(e != hipSuccess ? e : e2));
-        }
-    }
+    pic_status st = diag_range(ctx, mem, 0, ctx->np, gamma, px, py, pz, x, k_last, status);
+    if (st) return st;
     if (cnt) return read_counters(ctx, -1, cnt);
+    return PIC_OK;
+}
+
+pic_status pic_diag_r(pic_ctx *ctx, int32_t run, pic_mem mem, double *gamma, double *px,
+                      double *py, double *pz, double *x, int8_t *k_last, uint8_t *status,
+                      pic_counters *cnt)
+{
+    CTX_CHECK(ctx);
+    if (run < 0 || run >= ctx->nruns) return fail(ctx, PIC_E_ARG, "bad run %d", run);
+    const RunHost &R = ctx->runs[size_t(run)];
+    pic_status st = diag_range(ctx, mem, R.caller_off, R.np, gamma, px, py, pz, x, k_last, status);
+    if (st) return st;
+    if (cnt) return read_counters(ctx, run, cnt);
     return PIC_OK;
 }
 
@@ -1072,7 +1137,7 @@ pic_status pic_diag_noalloc(pic_ctx *ctx, double *gamma, double *px, double *py,
     if (any && np > 0) {
         diag_kernel<<<grid_for(ctx->slots, 256, 8192), 256, 0, ctx->stream>>>(
             ctx->perm, ctx->slots, ctx->x, ctx->px, ctx->py, ctx->pz, ctx->kold, ctx->status,
-            gamma ? d : nullptr, px ? d + n : nullptr, py ? d + 2 * n : nullptr,
+            int64_t(0), np, gamma ? d : nullptr, px ? d + n : nullptr, py ? d + 2 * n : nullptr,
             pz ? d + 3 * n : nullptr, x ? d + 4 * n : nullptr, k_last ? dk : nullptr,
             status ? ds : nullptr);
         LAUNCH_CHECK(ctx);

@@ -109,12 +109,13 @@ __global__ void __launch_bounds__(64 * WPG) push_wave_fp32c_kernel(PushArgs a)
     if (mine) {
         const double xi = (a.x[s] - R.x_origin) / R.dx;
         status = a.status[s];
-        if (status == PIC_PARTICLE_LIVE && xi >= 0.0 && xi < double(R.ncells)) {
+        if (status == PIC_PARTICLE_LIVE && xi >= 0.0 && xi < double(R.ncells) &&
+            !nonfinite_p(a.px[s], a.py[s], a.pz[s])) {
             const double fl = floor(xi);
             cell = int(fl);
             split(xi - fl, fr, frc);
         } else if (status == PIC_PARTICLE_LIVE) {
-            cell = -1;     // outside: flagged at the first step
+            cell = -1;     // outside or not finite: flagged at the first step
         }
         split(a.px[s], pxh, pxl);
         split(a.py[s], pyh, pyl);

@@ -180,6 +180,7 @@ __global__ void __launch_bounds__(64 * WPG)
         kold = a.kold[s];
         fold = kold < 0 ? -1.0 : ldexp(1.0, -2 * kold);
         status = a.status[s];
+        if (nonfinite_p(px, py, pz)) x = __builtin_nan("");
         if (KT && a.ktrace) {
             const int64_t u = a.perm[s] - a.kt_first;
             if (u >= 0 && u < a.kt_count) kt_u = u;

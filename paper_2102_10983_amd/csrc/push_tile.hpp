@@ -88,6 +88,10 @@ __global__ void __launch_bounds__(TILE) push_tile_kernel(PushArgs a)
     __syncthreads();
 
     const int S_run = run_steps(a, R, n0);
+    if (S_run > 0 && status == PIC_PARTICLE_LIVE && nonfinite_p(px, py, pz)) {
+        status = PIC_PARTICLE_LOST;
+        ++cnt.lost;
+    }
     for (int st = 0; st < S_run; ++st) {
         const int64_t n = n0 + st;
         Levels<P> lv;

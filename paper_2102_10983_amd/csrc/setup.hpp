@@ -245,10 +245,13 @@ __global__ void gather_state_kernel(const int32_t *__restrict__ perm, int64_t sl
     }
 }
 
+// Per-particle outputs of pic_diag in caller order, for the caller indices
+// u_lo .. u_lo + u_n - 1 (written at u - u_lo); null outputs are skipped.
 __global__ void diag_kernel(const int32_t *__restrict__ perm, int64_t slots,
                             const double *__restrict__ sx, const double *__restrict__ spx,
                             const double *__restrict__ spy, const double *__restrict__ spz,
                             const int8_t *__restrict__ skold, const uint8_t *__restrict__ sst,
+                            int64_t u_lo, int64_t u_n,
                             double *__restrict__ gamma, double *__restrict__ px,
                             double *__restrict__ py, double *__restrict__ pz,
                             double *__restrict__ x, int8_t *__restrict__ klast,
@@ -256,8 +259,8 @@ __global__ void diag_kernel(const int32_t *__restrict__ perm, int64_t slots,
 {
     for (int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; s < slots;
          s += int64_t(gridDim.x) * blockDim.x) {
-        const int32_t u = perm[s];
-        if (u < 0) continue;
+        const int64_t u = int64_t(perm[s]) - u_lo;
+        if (u < 0 || u >= u_n) continue;
         const double a = spx[s], b = spy[s], c = spz[s];
         if (gamma) gamma[u] = sqrt(1.0 + ((a * a + b * b) + c * c));
         if (px) px[u] = a;
@@ -267,6 +270,17 @@ __global__ void diag_kernel(const int32_t *__restrict__ perm, int64_t slots,
         if (klast) klast[u] = skold[s];
         if (status) status[u] = sst[s];
     }
+}
+
+// Strict mode: flag[0] := 1 if any of a[0 .. n) is not finite (flag is
+// cleared by the caller).
+__global__ void nonfinite_kernel(const double *__restrict__ a, int64_t n, int32_t *__restrict__ flag)
+{
+    bool bad = false;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * blockDim.x)
+        bad |= !__builtin_isfinite(a[i]);
+    if (bad) flag[0] = 1;
 }
 
 // Sum of the counter words over `rows` slots (all runs): out[j] = sum_r

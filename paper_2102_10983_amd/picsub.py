@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(PKG, "libpicsub.so")
 PIC_KHIST = 16
 PIC_K_MAX_LIMIT = 8
 STATUS = {0: "PIC_OK", 1: "PIC_E_ARG", 2: "PIC_E_DEVICE", 3: "PIC_E_NOMEM",
-          4: "PIC_E_LEVEL", 5: "PIC_E_STATE"}
+          4: "PIC_E_LEVEL", 5: "PIC_E_STATE", 6: "PIC_E_NUMERIC"}
 PRECISION = {"fp64": 0, "fp32c": 1, "fp64fast": 2}
 BINNING = {"none": 0, "ballot": 1, "learned": 2}
 MEM_HOST, MEM_DEVICE = 0, 1
@@ -26,7 +26,8 @@ MEM_HOST, MEM_DEVICE = 0, 1
 # every symbol the header declares
 EXPORTS = ("pic_create", "pic_destroy", "pic_last_error", "pic_particles_set",
            "pic_fields_load", "pic_fields_load_lattice", "pic_push_subcycled",
-           "pic_ktrace_set", "pic_diag", "pic_diag_noalloc", "pic_counters_reset",
+           "pic_ktrace_set", "pic_diag", "pic_diag_noalloc", "pic_diag_r", "pic_strict_set",
+           "pic_counters_reset",
            "pic_batch_create",
            "pic_fields_load_r", "pic_fields_load_lattice_r", "pic_source_set", "pic_advance",
            "pic_run_level", "pic_graph_capture", "pic_graph_launch", "pic_graph_release",
@@ -105,6 +106,9 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "pic_ktrace_set": ([vp, vp, i64, i32, i64, i64], C.c_int),
         "pic_diag": ([vp, C.c_int, vp, vp, vp, vp, vp, vp, vp, C.POINTER(Counters)], C.c_int),
         "pic_diag_noalloc": ([vp, vp, vp, vp, vp, vp, vp, vp, C.POINTER(Counters)], C.c_int),
+        "pic_diag_r": ([vp, i32, C.c_int, vp, vp, vp, vp, vp, vp, vp, C.POINTER(Counters)],
+                       C.c_int),
+        "pic_strict_set": ([vp, i32], C.c_int),
         "pic_counters_reset": ([vp], C.c_int),
         "pic_batch_create": ([vp, vp, i32, vp, C.POINTER(vp)], C.c_int),
         "pic_fields_load_r": ([vp, i32, i64, C.c_int, vp, vp], C.c_int),
@@ -497,6 +501,24 @@ class Pusher:
             out["k_last"].ctypes.data, out["status"].ctypes.data, C.byref(c)))
         out["counters"] = c.as_dict()
         return out
+
+    def diag_run(self, run: int) -> dict:
+        """pic_diag_r: host copies of one run's particles (caller order of
+        that run) and the run's counters."""
+        n = int(self.nums[run])
+        out = {k: np.empty(n) for k in ("gamma", "px", "py", "pz", "x")}
+        out["k_last"] = np.empty(n, dtype=np.int8)
+        out["status"] = np.empty(n, dtype=np.uint8)
+        c = Counters()
+        self._check(self._lib.pic_diag_r(
+            self._ctx, int(run), MEM_HOST,
+            *[out[k].ctypes.data for k in ("gamma", "px", "py", "pz", "x")],
+            out["k_last"].ctypes.data, out["status"].ctypes.data, C.byref(c)))
+        out["counters"] = c.as_dict()
+        return out
+
+    def strict_set(self, on: bool = True):
+        self._check(self._lib.pic_strict_set(self._ctx, 1 if on else 0))
 
     def diag_noalloc(self, keys=("gamma", "px", "py", "pz", "x", "k_last", "status"),
                      counters: bool = True) -> dict:

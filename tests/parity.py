@@ -51,13 +51,14 @@ def oracle_yee_fields(wl: W.Workload, steps: int):
 
 
 def oracle_run(wl, steps, idx=None, order=None, psi_max=None, trace=False, forced_k=None,
-               k_old=None, threads=0, fields=None):
+               k_old=None, threads=0, fields=None, k_max=8, state=None):
     idx = np.arange(wl.num) if idx is None else np.asarray(idx)
-    st = O.State(wl.x0[idx], wl.p0[0][idx], wl.p0[1][idx], wl.p0[2][idx],
+    x0, p0 = (wl.x0, wl.p0) if state is None else state
+    st = O.State(x0[idx], p0[0][idx], p0[1][idx], p0[2][idx],
                  k_old=None if k_old is None else np.asarray(k_old)[idx])
     cnt = O.Counters()
     fs = oracle_fields(wl) if fields is None else fields
-    kt, pt = O.push(oracle_params(wl, order, psi_max), fs, st, 0, steps,
+    kt, pt = O.push(oracle_params(wl, order, psi_max, k_max), fs, st, 0, steps,
                     trace=trace, psi_trace=trace, forced_k=forced_k, counters=cnt,
                     threads=threads)
     return st, cnt, kt, pt
@@ -73,7 +74,7 @@ def errors(gx, gpx, gpy, gpz, st: O.State, x0):
 
 
 def compare(wl, steps, gdiag, idx, tol, g_ktrace=None, order=None, psi_max=None,
-            flip_rel=1e-9, fields=None, keep_each=False):
+            flip_rel=1e-9, fields=None, keep_each=False, k_max=8, state=None):
     """Compare device results (caller order, full arrays) on particles idx.
 
     flip_rel bounds how far from a threshold psi_max 4^k the first differing
@@ -83,7 +84,8 @@ def compare(wl, steps, gdiag, idx, tol, g_ktrace=None, order=None, psi_max=None,
     e_p under "e_p_each"); raises AssertionError on a violation."""
     idx = np.asarray(idx)
     st, cnt, kt, pt = oracle_run(wl, steps, idx, order=order, psi_max=psi_max,
-                                 trace=g_ktrace is not None, fields=fields)
+                                 trace=g_ktrace is not None, fields=fields, k_max=k_max,
+                                 state=state)
     gx, gpx, gpy, gpz = (gdiag[k][idx] for k in ("x", "px", "py", "pz"))
     out = {"n": len(idx), "flips": 0, "bitwise": 0}
     same = np.ones(len(idx), dtype=bool)
@@ -105,10 +107,10 @@ def compare(wl, steps, gdiag, idx, tol, g_ktrace=None, order=None, psi_max=None,
             out["worst_flip"] = worst
             fst, _, _, _ = oracle_run(wl, steps, idx[~same], order=order, psi_max=psi_max,
                                       forced_k=np.ascontiguousarray(gk[:, ~same]),
-                                      fields=fields)
+                                      fields=fields, k_max=k_max, state=state)
             st.x[~same], st.px[~same], st.py[~same], st.pz[~same] = fst.x, fst.px, fst.py, fst.pz
             st.status[~same] = fst.status
-    e_p, e_x = errors(gx, gpx, gpy, gpz, st, wl.x0[idx])
+    e_p, e_x = errors(gx, gpx, gpy, gpz, st, (wl.x0 if state is None else state[0])[idx])
     if keep_each:
         out["e_p_each"] = e_p
     out["max_e_p"] = float(e_p.max()) if len(idx) else 0.0

@@ -28,12 +28,13 @@ def torch_gpu():
     return torch
 
 
-@pytest.mark.parametrize("num,psi", [(1 << 20, 0.01), (1 << 24, 0.003)],
-                         ids=["2p20-psi0.01", "2p24-psi0.003"])
+@pytest.mark.parametrize("num,psi", [(1 << 20, 0.01), (1 << 24, 0.01), (1 << 24, 0.003)],
+                         ids=["2p20-psi0.01", "2p24-psi0.01", "2p24-psi0.003"])
 def test_thermal_load_subsample(torch_gpu, num, psi):
     """Thermal electrons (10 keV) over 200 wavelengths, a0 = 150, 100 periods,
-    learned order: 2^20 at Psi_max = 0.01 and the full 2^24 at 0.003; 4096
-    consecutive electrons (caller order) checked against the oracle."""
+    learned order: 2^20 at Psi_max = 0.01 and the full 2^24 at 0.01 and
+    0.003; 4096 consecutive electrons (caller order) checked against the
+    oracle."""
     torch = torch_gpu
     from paper_2102_10983_amd import predictor, runner
     from parity import compare
@@ -82,6 +83,46 @@ def test_batch_runs(torch_gpu, run_index):
     _say(f"batch run {run_index} ({wl.name}, {wl.num} electrons):",
          {k: v for k, v in res.items() if k != "oracle_counters"})
     assert res["max_e_p"] < 1e-6     # the bar is 1e-5
+
+
+def test_batch_full_scale_sampled(torch_gpu):
+    """The full batch (64 uneven runs, 2.0e7 electrons, 50 periods each, one
+    window per run, learned order): up to 4096 electrons of each of three
+    runs of different a0 and T/dt against the oracle."""
+    torch = torch_gpu
+    from paper_2102_10983_amd import predictor, runner
+    from parity import compare
+    wls = W.batch_case(seed=3, nruns=64, periods=50.0)
+    S = max(w.steps for w in wls)
+    br = runner.BatchRun(wls, S=S, precision="fp64fast", binning="none")
+    br.reset()
+    predictor.Predictor.load().prebin(br.pusher, [w.a0 for w in wls])
+    picks = (5, 29, 52)
+    bufs = []
+    for r in picks:
+        wl = wls[r]
+        off = int(sum(w.num for w in wls[:r]))
+        m = min(4096, wl.num)
+        buf = torch.full((wl.steps, m), -2, dtype=torch.int8, device="cuda")
+        bufs.append((r, off, m, buf))
+    # one trace buffer at a time: run the pass once per sampled run
+    out = []
+    for r, off, m, buf in bufs:
+        br.reset()
+        predictor.Predictor.load().prebin(br.pusher, [w.a0 for w in wls])
+        br.pusher.ktrace_set(buf, 0, off)
+        br.run_all()
+        out.append((r, off, m, buf.cpu().numpy(), br.diag()))
+    br.close()
+    for r, off, m, kt, d in out:
+        wl = wls[r]
+        sub = {k: d[k][off:off + wl.num] for k in ("x", "px", "py", "pz", "status")}
+        full = np.full((wl.steps, wl.num), -3, dtype=np.int8)
+        full[:, :m] = kt
+        res = compare(wl, wl.steps, sub, np.arange(m), TOL, g_ktrace=full, flip_rel=1e-9)
+        _say(f"full batch run {r} ({wl.name}, {wl.num} electrons):",
+             {k: v for k, v in res.items() if k != "oracle_counters"})
+        assert res["max_e_p"] < 1e-6     # the bar is 1e-5
 
 
 def test_benchmark_configuration_sampled(torch_gpu):
