@@ -23,8 +23,25 @@ def _declared():
 
 def test_header_declares_the_boundary():
     names = _declared()
-    for required in ("pic_create", "pic_fields_load", "pic_push_subcycled", "pic_diag"):
-        assert required in names
+    for required in ("pic_create", "pic_destroy", "pic_last_error", "pic_particles_set",
+                     "pic_fields_load", "pic_fields_load_lattice", "pic_push_subcycled",
+                     "pic_diag", "pic_batch_create", "pic_fields_load_r", "pic_diag_r",
+                     "pic_advance", "pic_predictor_set", "pic_mlp_forward", "pic_mlp_grad",
+                     "pic_mlp_adam", "pic_state_export", "pic_state_import", "pic_strict_set"):
+        assert required in names, required
+
+
+def test_header_constants():
+    """Status codes (PIC_E_NUMERIC for strict mode), the k_max limit of 12
+    and the no-allocation entry point's particle limit."""
+    src = open(os.path.join(ROOT, "include", "picsub.h")).read()
+    codes = dict(re.findall(r"(PIC_\w+)\s*=\s*(\d+)", src))
+    assert [codes[c] for c in ("PIC_OK", "PIC_E_ARG", "PIC_E_DEVICE", "PIC_E_NOMEM",
+                               "PIC_E_LEVEL", "PIC_E_STATE", "PIC_E_NUMERIC")] == list("0123456")
+    assert re.search(r"#define PIC_K_MAX_LIMIT 12\b", src)
+    assert re.search(r"#define PIC_DIAG_NOALLOC_MAX_NP 1572864\b", src)
+    from paper_2102_10983_amd import picsub
+    assert picsub.STATUS[6] == "PIC_E_NUMERIC"
 
 
 def test_library_exports_every_declared_symbol():
