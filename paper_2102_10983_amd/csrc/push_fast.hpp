@@ -20,7 +20,12 @@
 // 1/gamma from v_rsq_f64 and the Boris denominator from v_rcp_f64, each
 // refined by one Newton step; x is carried in node units.  p_z never
 // changes in this geometry (E along y, B along z), so 1 + p_z^2 is a
-// constant of each lane.
+// constant of each lane.  When a wavefront sub-cycles, its LDS window is
+// rewritten once per step as the coefficients of each node's interpolating
+// polynomial in u = s - 1/2 (the same polynomial as the Lagrange form), so a
+// sub-step evaluates it by Horner's rule at u = (j - 1) / 4^k instead of
+// loading the weights of (k, j).  Completed sub-cycled steps are counted per
+// k in the wavefront's LDS, one distinct k at a time.
 #pragma once
 
 #include "common.hpp"
@@ -121,6 +126,78 @@ __device__ __forceinline__ double comb_lds(const double *p, int field, const W &
     return v;
 }
 
+// The temporal interpolant of one node over the levels n - P .. n
+// (Eqs. (lagrange1-2), (lagrange1-3)) written in the monomial basis of
+// u = s - 1/2 (u = 0 at the time of x_n, u in [0, 1) over a sub-cycled step):
+// N(u) = sum_m a_m u^m with a = C F, F the level values, C the inverse of the
+// Vandermonde matrix of the level times (E: u = j - P, B: u = j - P + 1/2).
+// The entries are exact rationals; C[B][0][.] are the weights at s = 1/2.
+template <int P>
+__device__ constexpr double mono_c(int field, int m, int j)
+{
+    if constexpr (P == 1) {
+        constexpr double e[2][2] = {{0.0, 1.0}, {-1.0, 1.0}};
+        constexpr double b[2][2] = {{0.5, 0.5}, {-1.0, 1.0}};
+        return field ? b[m][j] : e[m][j];
+    } else if constexpr (P == 3) {
+        constexpr double e[4][4] = {{0.0, 0.0, 0.0, 1.0},
+                                    {-1.0 / 3, 3.0 / 2, -3.0, 11.0 / 6},
+                                    {-1.0 / 2, 2.0, -5.0 / 2, 1.0},
+                                    {-1.0 / 6, 1.0 / 2, -1.0 / 2, 1.0 / 6}};
+        constexpr double b[4][4] = {{1.0 / 16, -5.0 / 16, 15.0 / 16, 5.0 / 16},
+                                    {1.0 / 24, -1.0 / 8, -7.0 / 8, 23.0 / 24},
+                                    {-1.0 / 4, 5.0 / 4, -7.0 / 4, 3.0 / 4},
+                                    {-1.0 / 6, 1.0 / 2, -1.0 / 2, 1.0 / 6}};
+        return field ? b[m][j] : e[m][j];
+    } else {
+        constexpr double e[6][6] = {{0.0, 0.0, 0.0, 0.0, 0.0, 1.0},
+                                    {-1.0 / 5, 5.0 / 4, -10.0 / 3, 5.0, -5.0, 137.0 / 60},
+                                    {-5.0 / 12, 61.0 / 24, -13.0 / 2, 107.0 / 12, -77.0 / 12, 15.0 / 8},
+                                    {-7.0 / 24, 41.0 / 24, -49.0 / 12, 59.0 / 12, -71.0 / 24, 17.0 / 24},
+                                    {-1.0 / 12, 11.0 / 24, -1.0, 13.0 / 12, -7.0 / 12, 1.0 / 8},
+                                    {-1.0 / 120, 1.0 / 24, -1.0 / 12, 1.0 / 12, -1.0 / 24, 1.0 / 120}};
+        constexpr double b[6][6] = {{7.0 / 256, -45.0 / 256, 63.0 / 128, -105.0 / 128, 315.0 / 256, 63.0 / 256},
+                                    {71.0 / 1920, -29.0 / 128, 37.0 / 64, -143.0 / 192, -67.0 / 128, 563.0 / 640},
+                                    {-3.0 / 32, 59.0 / 96, -85.0 / 48, 49.0 / 16, -269.0 / 96, 95.0 / 96},
+                                    {-7.0 / 48, 43.0 / 48, -55.0 / 24, 71.0 / 24, -91.0 / 48, 23.0 / 48},
+                                    {-1.0 / 16, 17.0 / 48, -19.0 / 24, 7.0 / 8, -23.0 / 48, 5.0 / 48},
+                                    {-1.0 / 120, 1.0 / 24, -1.0 / 12, 1.0 / 12, -1.0 / 24, 1.0 / 120}};
+        return field ? b[m][j] : e[m][j];
+    }
+}
+
+// Replace the level rows of the LDS window (row 2j: E of level j, 2j + 1: B,
+// nodes 0 .. nn - 1) by the monomial coefficients (row 2m: a_m of E, 2m + 1:
+// of B), one node and field per lane.
+template <int P>
+__device__ __forceinline__ void window_to_monomial(double *sw, int nn, int lane)
+{
+    for (int c = lane; c < 2 * nn; c += 64) {
+        const int f = c >= nn ? 1 : 0;
+        double *col = sw + f * WWIN + (c - f * nn);
+        double F[P + 1];
+#pragma unroll
+        for (int j = 0; j <= P; ++j) F[j] = col[2 * j * WWIN];
+#pragma unroll
+        for (int m = 0; m <= P; ++m) {
+            double v = mono_c<P>(f, m, 0) * F[0];
+#pragma unroll
+            for (int j = 1; j <= P; ++j) v = fma(mono_c<P>(f, m, j), F[j], v);
+            col[2 * m * WWIN] = v;
+        }
+    }
+}
+
+// N(u) of one node from its coefficient column (rows 2m + field).
+template <int P>
+__device__ __forceinline__ double horner_lds(const double *p, int field, double u)
+{
+    double v = p[(2 * P + field) * WWIN];
+#pragma unroll
+    for (int m = P - 1; m >= 0; --m) v = fma(v, u, p[(2 * m + field) * WWIN]);
+    return v;
+}
+
 // Register budget: the compiler's own allocation (94 VGPRs at order 1, 120 at
 // order 3, 124 at order 5) gives 5, 4 and 4 wavefronts per SIMD; OCC > 0 asks
 // for OCC wavefronts per SIMD (pic_tune.occupancy), paid for with spills.  KT: the k trace compiled in
@@ -135,11 +212,15 @@ __global__ void __launch_bounds__(64 * WPG)
     constexpr int STRIDE = 2 * (P + 1);               // weight-table entry
     static_assert(PF_NW == 16, "the step-ahead load maps lane bits 4, 5 to field, level");
     __shared__ double sw_all[WPG][ROWS * WWIN];
+    __shared__ uint32_t shist_all[WPG][PIC_K_MAX_LIMIT + 1];   // completed steps per k > 0
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int pos = blockIdx.x * WPG + wv;
     if (pos >= a.ngroups) return;                      // whole wavefront: no barrier below
     double *sw = sw_all[wv];
+    uint32_t *shist = shist_all[wv];
+    if (lane <= PIC_K_MAX_LIMIT) shist[lane] = 0;
+    wave_lds_sync();
     const int g = __builtin_amdgcn_readfirstlane(a.group_order[pos]);
     const int run = __builtin_amdgcn_readfirstlane(a.group_run[g]);
     const int prio = __builtin_amdgcn_readfirstlane(a.group_prio[g]);
@@ -167,7 +248,9 @@ __global__ void __launch_bounds__(64 * WPG)
     const bool mine = s - p_off < np;
     double x = 0, px = 0, py = 0, pz = 0, onepz = 1, ig = 1;   // x in node units
     int kold = 0;
-    double fold = 1.0;               // dt*_old / dt
+    // q dt_p / 2 of a k = 0 step: dt_p = (dt*_old + dt) / 2 (Sec. IV), which is
+    // dt unless the previous step was sub-cycled
+    double c1k0 = c0;
     uint8_t status = PIC_PARTICLE_LOST;
     int64_t kt_u = -1;
     if (mine) {
@@ -178,7 +261,7 @@ __global__ void __launch_bounds__(64 * WPG)
         onepz = fma(pz, pz, 1.0);
         ig = rsq_1nr(fma(px, px, fma(py, py, onepz)));
         kold = a.kold[s];
-        fold = kold < 0 ? -1.0 : ldexp(1.0, -2 * kold);
+        if (kold > 0) c1k0 = q4 * (ldexp(1.0, -2 * kold) + 1.0);
         status = a.status[s];
         if (nonfinite_p(px, py, pz)) x = __builtin_nan("");
         if (KT && a.ktrace) {
@@ -310,9 +393,29 @@ __global__ void __launch_bounds__(64 * WPG)
         }
         const bool heavy = live && k > 0;
 
+        // E of level n at x_n for a k = 0 step (s = 1/2 is the time of level n:
+        // E's weights are (0, .., 0, 1)), read before the window is converted
+        double Ek = 0.0;
+        if (live & (k == 0)) {
+            const double uE = x - 0.5;
+            const double flE = floor(uE);
+            const int iE = int(flE);
+            double e0, e1;
+            if (use_win) {
+                const double *p = sw + (2 * P) * WWIN + (iE - wlo);
+                e0 = p[0];
+                e1 = p[1];
+            } else {
+                e0 = ringE[lv.off[P] + iE];
+                e1 = ringE[lv.off[P] + iE + 1];
+            }
+            Ek = tent_fma(uE - flE, e0, e1);
+        }
+
         // A sub-cycled step outside the step-ahead window stages its own.
         bool lds = use_win;
         int base = wlo;
+        int nwin = PF_NW;
         if (!use_win && wany(heavy)) {
             const int lo = max(__builtin_amdgcn_readfirstlane(
                                    wave_min(heavy ? cell - margin : INT_MAX)), 0);
@@ -329,50 +432,48 @@ __global__ void __launch_bounds__(64 * WPG)
                 }
                 wave_lds_sync();
                 base = lo;
+                nwin = hi - lo + 1;
                 lds = true;
             }
+        }
+        // sub-steps read the window's nodes as polynomials in u
+        if (lds && hmask) {
+            wave_lds_sync();
+            window_to_monomial<P>(sw, nwin, lane);
+            wave_lds_sync();
         }
 
         bool done = false;
         double gst = 1.0, swork = 0.0;     // diagnostics: gamma at the step start, step work
         if (live) {
             moved = true;
+            const int kprev = kold;
             kold = k;
             if (deph) gst = gamma_of(px, py, pz);
-            // dt*_new / dt and dt*_old / dt (negative: cold start, p lags
-            // x by half of this step's sub-step)
-            const double fnew = ldexp(1.0, -2 * k);
-            const double c1 = q4 * ((fold < 0.0 ? fnew : fold) + fnew);   // transition push
-            fold = fnew;
-            const double rdx = dtdx * fnew;
-            const double dt_new = dt * fnew;
             if (k == 0) {
-                // s = 1/2 is the time of level n: E's weights are (0, .., 0, 1)
-                const double uE = x - 0.5;
-                const double flE = floor(uE);
-                const int iE = int(flE);
-                double e0, e1;
-                if (use_win) {
-                    const double *p = sw + (2 * P) * WWIN + (iE - wlo);
-                    e0 = p[0];
-                    e1 = p[1];
-                } else {
-                    e0 = ringE[lv.off[P] + iE];
-                    e1 = ringE[lv.off[P] + iE + 1];
-                }
-                const double Ek = tent_fma(uE - flE, e0, e1);
+                const double c1 = c1k0;
+                c1k0 = c0;
                 const double vb = deph ? py * ig : 0.0;
                 boris_fma(c1, Ek, Bd, onepz, px, py);
                 ig = rsq_1nr(fma(px, px, fma(py, py, onepz)));
-                x = fma(rdx, px * ig, x);
+                x = fma(dtdx, px * ig, x);
                 if (deph) swork = sub_step_work(c1, Ek, vb, py * ig);
                 done = true;
             } else {
+                // dt*_new / dt and dt*_old / dt (cold start: p lags x by half
+                // of this step's sub-step)
+                const double fnew = ldexp(1.0, -2 * k);
+                const double fold = kprev < 0 ? fnew : ldexp(1.0, -2 * kprev);
+                const double c1 = q4 * (fold + fnew);          // transition push
+                c1k0 = q4 * (fnew + 1.0);                      // for a k = 0 step next
+                const double rdx = dtdx * fnew;
+                const double dt_new = dt * fnew;
                 const int nsub = 1 << (2 * k);
                 const double cn = 0.5 * qm * dt_new;
                 const double *Wk = a.wtab + wtab_offset(k) * STRIDE;
+                double u = 0.0;                                // s - 1/2 of sub-step j
                 done = true;
-                for (int j = 1; j <= nsub; ++j, Wk += STRIDE) {
+                for (int j = 1; j <= nsub; ++j, Wk += STRIDE, u += fnew) {
                     if (j > 1 && !(x >= 0.5 && x < ncm1)) {
                         done = false;
                         break;
@@ -386,10 +487,10 @@ __global__ void __launch_bounds__(64 * WPG)
                     if (lds) {
                         const double *pb = sw + (ib - base);
                         const double *pe = sw + (ie - base);
-                        bb0 = comb_lds<P>(pb, 1, Wk + P + 1);
-                        bb1 = comb_lds<P>(pb + 1, 1, Wk + P + 1);
-                        e0 = comb_lds<P>(pe, 0, Wk);
-                        e1 = comb_lds<P>(pe + 1, 0, Wk);
+                        bb0 = horner_lds<P>(pb, 1, u);
+                        bb1 = horner_lds<P>(pb + 1, 1, u);
+                        e0 = horner_lds<P>(pe, 0, u);
+                        e1 = horner_lds<P>(pe + 1, 0, u);
                     } else {
                         bb0 = comb_fma<P>(ringB, lv.off, ib, Wk + P + 1);
                         bb1 = comb_fma<P>(ringB, lv.off, ib + 1, Wk + P + 1);
@@ -410,7 +511,14 @@ __global__ void __launch_bounds__(64 * WPG)
         // grid inside a step
         cnt.steps[0] += __popcll(lmask & ~hmask);
         if (hmask) {
-            cnt.steps_heavy(done, k);
+            // completed sub-cycled steps per k, one distinct k at a time
+            uint64_t m = wballot(done & (k > 0));
+            while (m) {
+                const int kk = __builtin_amdgcn_readlane(k, __ffsll((unsigned long long)m) - 1);
+                const uint64_t mk = m & wballot(k == kk);
+                if (lane == 0) atomicAdd(&shist[kk], uint32_t(__popcll(mk)));
+                m &= ~mk;
+            }
             cnt.lost += __popcll(wballot(live & !done));
         }
         if (deph && done) {
@@ -448,7 +556,12 @@ __global__ void __launch_bounds__(64 * WPG)
             a.werr[s] = wem;
         }
     }
-    cnt.flush(a.cnt + (int64_t(run) * NSLOT + pos % NSLOT) * NCNT, lane);
+    uint64_t *slot = a.cnt + (int64_t(run) * NSLOT + pos % NSLOT) * NCNT;
+    if (lane >= 1 && lane <= PIC_K_MAX_LIMIT) {
+        const uint32_t v = shist[lane];
+        if (v) atomicAdd(reinterpret_cast<unsigned long long *>(slot + lane), v);
+    }
+    cnt.flush(slot, lane);
 }
 
 }  // namespace picsub
