@@ -218,6 +218,10 @@ class Pass:
         if self.binning == "learned":
             self.predictor.prebin(self.pusher, self.a0, n=None if self.batch else 0,
                                   width=self.pb_width)
+        elif self.binning == "psi":
+            from paper_2102_10983_amd import predictor as PR
+            score = PR.psi_score(self.pusher, self.a0, wl.dt, wl.psi_max, n=0)
+            self.pusher.prebin(score, nbuckets=1, width=self.pb_width)
         if self.batch:
             for _ in range(run.windows):
                 if events is not None:
@@ -314,7 +318,10 @@ def main():
     ap.add_argument("--fields", default="lattice", choices=("lattice", "yee"),
                     help="single runs: field levels sampled from the prescribed wave "
                          "(perfectly propagating PIC) or made by the Yee solver (standard PIC)")
-    ap.add_argument("--binning", default="learned", choices=("none", "ballot", "learned"))
+    ap.add_argument("--binning", default="learned", choices=("none", "ballot", "learned", "psi"),
+                    help="group order: slot (position) order, the compaction kernel, the "
+                         "learned load predictor, or the step-0 value of the Psi criterion "
+                         "(a non-learned control)")
     ap.add_argument("--num", type=int, default=0,
                     help="electrons (large: 2^20, stress: 2^24, predictor: 2^22; batch: scale "
                          "factor x 1e6)")
@@ -434,6 +441,8 @@ def main():
     if not args.no_compare:
         legs = [("plain binning, same precision", args.workload, args.precision, "none",
                  args.fields, args.steps),
+                ("groups ordered by the step-0 Psi criterion (non-learned control), same "
+                 "precision", args.workload, args.precision, "psi", args.fields, args.steps),
                 ("plain FP64 push (IEEE div/sqrt)", args.workload, "fp64", "none", args.fields,
                  args.steps),
                 ("FP32-compensated push, same binning", args.workload, "fp32c", args.binning,
@@ -449,9 +458,16 @@ def main():
                 if name != args.workload:
                     legs.append((f"workload {name}, same precision and binning", name,
                                  args.precision, args.binning, "lattice", 1))
+                    if name == "stress":
+                        legs.append((f"workload {name}, plain binning", name, args.precision,
+                                     "none", "lattice", 1))
+                        legs.append((f"workload {name}, step-0 Psi order", name,
+                                     args.precision, "psi", "lattice", 1))
         for label, wname, prec, binning, fields, nsteps in legs:
             if (wname == args.workload and prec == args.precision and binning == args.binning
                     and fields == args.fields):
+                continue
+            if binning == "psi" and wname == "batch":
                 continue
             lwl, ldesc = (wl, wdesc) if wname == args.workload else make_workload(wname, args)
             lsteps = max(w.steps for w in lwl) if isinstance(lwl, list) else lwl.steps

@@ -92,6 +92,19 @@ class Predictor:
         return s
 
 
+# -- a non-learned control ----------------------------------------------------
+def psi_score(pusher: picsub.Pusher, a0, dt: float, psi_max: float, n=None):
+    """Order score without learning: log2 of psi0 / psi_max at level n,
+    psi0 = |q| dt |B_z| / (2 gamma) from the features (|B_z| at the particle
+    and gamma), clamped below at 0.  It is log2 of the sub-steps the Psi
+    criterion (Sec. IV) gives the particle's next step, i.e. a predictor of
+    the next step's load only; NaN (lightest) for lost particles."""
+    import torch
+    f = pusher.features(a0, n=n)
+    psi0 = 0.5 * dt * f[:, 1].double() / f[:, 4].double()
+    return torch.clamp(torch.log2(psi0 / psi_max), min=0.0).float().contiguous()
+
+
 # -- training data -----------------------------------------------------------
 def traced_load(run, steps: int, chunk: int = 500):
     """Run `steps` steps from the current state with a k trace of every
@@ -128,6 +141,25 @@ def collect(wl: W.Workload, horizon: int | None = None, precision: str = "fp64fa
     keep = (status == 0) & (tot > 0)
     target = torch.log2(tot.to(torch.float64) / steps).to(torch.float32)
     return feat[keep].cpu().numpy(), target[keep].cpu().numpy()
+
+
+def spec_workloads(nruns: int = 40, num: int = 1 << 18, periods: float = 100.0,
+                   seed: int = 600):
+    """The training set: nruns runs of num electrons (1.05e7 samples by
+    default), a0 log-uniform in [1, 150], T/dt from {40, 75, 150}, electrons
+    at rest or thermal (2 or 10 keV), spread over 50 wavelengths on a grid
+    long enough for the run; seeds disjoint from every evaluation case."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for r in range(nruns):
+        a0 = math.exp(rng.uniform(0.0, math.log(150.0)))
+        n_t = int((40, 75, 150)[int(rng.integers(0, 3))])
+        theta = (0.0, 2.0 / 511.0, 10.0 / 511.0)[int(rng.integers(0, 3))]
+        ncells = int(math.ceil((50.0 + periods + 2.0) * n_t * 100 / 101)) + 16
+        out.append(W.make_workload(f"train{r} a0={a0:.3g} T/dt={n_t} theta={theta:.3g}", num,
+                                   a0, n_t, ncells, periods, 3, 0.01, 50.0,
+                                   seed=seed + 1 + r, theta=theta))
+    return out
 
 
 def training_workloads(num: int = 1 << 18, periods: float = 100.0):
@@ -201,6 +233,9 @@ def main(argv=None):
     ap.add_argument("--num", type=int, default=1 << 18)
     ap.add_argument("--periods", type=float, default=100.0)
     ap.add_argument("--steps", type=int, default=3000)
+    ap.add_argument("--runs", type=int, default=40, help="runs of the training set")
+    ap.add_argument("--legacy", action="store_true",
+                    help="the earlier set: seven runs at a0 in {30, 80, 110, 150}, T/dt = 75")
     args = ap.parse_args(argv)
     if not args.train:
         ap.print_help()
@@ -210,7 +245,9 @@ def main(argv=None):
         print(*a, flush=True)
     feats, targets = [], []
     t0 = time.time()
-    for wl in training_workloads(args.num, args.periods):
+    wls = (training_workloads(args.num, args.periods) if args.legacy
+           else spec_workloads(args.runs, args.num, args.periods))
+    for wl in wls:
         f, t = collect(wl)
         log(f"{wl.name}: {len(t)} samples, target mean {t.mean():.4f} sd {t.std():.4f} "
             f"({time.time() - t0:.1f} s)")
@@ -220,7 +257,7 @@ def main(argv=None):
     target = np.concatenate(targets)
     p = train(feat, target, steps=args.steps, log=log)
     p.meta = {"horizon_periods": args.periods, "samples": int(len(target)),
-              "workloads": [wl.name for wl in training_workloads(args.num, args.periods)],
+              "workloads": [wl.name for wl in wls],
               "target": "log2 mean sub-steps per step over the horizon"}
     p.save(args.out)
     log(f"saved {args.out} ({time.time() - t0:.1f} s)")
