@@ -257,7 +257,8 @@ int orc_push(const orc_params *prm, const orc_fields *f, int64_t np,
              double *x, double *px, double *py, double *pz,
              int8_t *k_old, uint8_t *status, int64_t n0, int32_t nsteps,
              const int8_t *forced_k, int8_t *k_trace, double *psi_trace,
-             double *work, double *werr, orc_counters *cnt, int32_t nthreads)
+             double *work, double *werr, const double *r0, double *rmax, double *gmax,
+             orc_counters *cnt, int32_t nthreads)
 {
     if (!prm || !f || np < 0 || nsteps < 0) return -1;
     if (prm->order < 1 || prm->order > ORC_MAX_ORDER) return -1;
@@ -304,6 +305,16 @@ int orc_push(const orc_params *prm, const orc_fields *f, int64_t np,
                     double d = fabs((g_end - g_start) - sw);
                     if (work) work[i] += sw;
                     if (werr && d > werr[i]) werr[i] = d;
+                }
+                if (rc == 0 && ((r0 && rmax) || gmax)) {
+                    /* a completed step: dephasing error |R - R0| / R0, R = gamma -
+                     * p_x (Sec. IV, Eq. (R error)), and the largest gamma */
+                    double g_end = sqrt(1.0 + ((px[i] * px[i] + py[i] * py[i]) + pz[i] * pz[i]));
+                    if (r0 && rmax) {
+                        double dr = fabs((g_end - px[i]) - r0[i]) / r0[i];
+                        if (dr > rmax[i]) rmax[i] = dr;
+                    }
+                    if (gmax && g_end > gmax[i]) gmax[i] = g_end;
                 }
                 if (rc == 1) {
                     status[i] = ORC_LOST;

@@ -117,6 +117,10 @@ void orc_boris(double qm, double dtp, double E, double B,
  * v_after) per sub-step) is added to work[i], and werr[i] keeps the
  * largest |(gamma_end - gamma_start) - step work| (kinetic energy change
  * against work, in m c^2).
+ * r0, rmax (np each, may be NULL): after every completed step rmax[i]
+ * keeps the largest |R - r0[i]| / r0[i], R = gamma - p_x of the momentum
+ * (the dephasing error of Sec. IV, Eq. (R error)); gmax (may be NULL) keeps
+ * the largest gamma.
  * k_old[i] < 0 means "no previous sub-step": the first transition push
  * then uses dt*_new.  forced_k ([nsteps][np], may be NULL) replaces the
  * decision; k_trace and psi_trace ([nsteps][np], may be NULL) record the
@@ -127,7 +131,8 @@ int orc_push(const orc_params *prm, const orc_fields *f, int64_t np,
              double *x, double *px, double *py, double *pz,
              int8_t *k_old, uint8_t *status, int64_t n0, int32_t nsteps,
              const int8_t *forced_k, int8_t *k_trace, double *psi_trace,
-             double *work, double *werr, orc_counters *cnt, int32_t nthreads);
+             double *work, double *werr, const double *r0, double *rmax, double *gmax,
+             orc_counters *cnt, int32_t nthreads);
 
 /* number of OpenMP threads the library would use */
 int32_t orc_max_threads(void);

@@ -76,7 +76,8 @@ def lib():
                                C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                C.c_void_p, C.c_void_p, C.c_int64, C.c_int32,
                                C.c_void_p, C.c_void_p, C.c_void_p,
-                               C.c_void_p, C.c_void_p, C.POINTER(Counters), C.c_int32]
+                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                               C.POINTER(Counters), C.c_int32]
         L.orc_push.restype = C.c_int
         L.orc_max_threads.restype = C.c_int32
         _lib = L
@@ -174,11 +175,15 @@ class State:
 
 def push(prm: Params, fs: FieldSource, st: State, n0: int, nsteps: int, *,
          forced_k=None, trace=False, psi_trace=False, counters: Counters | None = None,
-         threads: int = 0, work=None, werr=None):
+         threads: int = 0, work=None, werr=None, r0=None, rmax=None, gmax=None):
     """Advance the state in place; returns (k_trace, psi_trace) arrays or None.
     work, werr: float64 arrays of st.num updated in place (App. B energy
-    accounting, see orc_push)."""
-    for a in (work, werr):
+    accounting); r0, rmax: the dephasing error of Eq. (R error) against r0,
+    running maximum kept in rmax; gmax: running maximum of gamma (see
+    orc_push)."""
+    if r0 is not None:
+        r0 = np.ascontiguousarray(r0, dtype=np.float64)
+    for a in (work, werr, rmax, gmax):
         if a is not None:
             assert a.dtype == np.float64 and a.shape == (st.num,) and a.flags.c_contiguous
     kt = np.empty((nsteps, st.num), dtype=np.int8) if trace else None
@@ -190,7 +195,7 @@ def push(prm: Params, fs: FieldSource, st: State, n0: int, nsteps: int, *,
     rc = lib().orc_push(C.byref(prm), C.byref(fs.s), st.num, _ptr(st.x), _ptr(st.px),
                         _ptr(st.py), _ptr(st.pz), _ptr(st.k_old), _ptr(st.status),
                         n0, nsteps, _ptr(fk), _ptr(kt), _ptr(pt), _ptr(work), _ptr(werr),
-                        C.byref(cnt), threads)
+                        _ptr(r0), _ptr(rmax), _ptr(gmax), C.byref(cnt), threads)
     if rc != 0:
         raise ValueError(f"orc_push failed ({rc})")
     return kt, pt

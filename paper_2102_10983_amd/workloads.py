@@ -83,23 +83,32 @@ def yee_lattice(n_t: int, r: int = 101, q: int = 100, j0: int = 0) -> Lattice:
                    aB=2 * q, bB=-2 * r, cB=q + j0)
 
 
+GAUSS_XI0 = 160.0 * math.pi      # pulse centre, relative to the electrons' initial phase
+GAUSS_SIGMA = 8.0 * math.pi
+GAUSS_MARGIN = 64.0 * math.pi    # phase covered beyond the pulse on either side
+
+
 def plane_wave_table(lat: Lattice, a0: float, kind: str = "flat",
-                     xi0: float = 160.0 * math.pi, sigma: float = 8.0 * math.pi,
-                     m_lo: int = 0, m_count: int | None = None):
+                     xi0: float = GAUSS_XI0, sigma: float = GAUSS_SIGMA,
+                     m_lo: int | None = None, m_count: int | None = None):
     """Table of E_y = B_z = -da/dxi on the lattice.
 
     Returns (table, M, shift): the value at lattice index m is
     table[(m - shift) mod M].  For a flat wave M is one period and
     shift = 0.  For the Gaussian pulse the table spans m_count points
-    starting at m_lo (zero outside the pulse), and shift = m_lo.
+    starting at m_lo (by default the phases -GAUSS_MARGIN .. xi0 + 9 sigma +
+    GAUSS_MARGIN, so that no node of a grid near the electrons wraps
+    around), and shift = m_lo.
     """
     if kind == "flat":
         m = np.arange(lat.period, dtype=np.int64)
         xi = m.astype(np.float64) * lat.unit
         return -a0 * np.cos(xi), lat.period, 0
     if kind == "gauss":
+        if m_lo is None:
+            m_lo = -int(math.ceil(GAUSS_MARGIN / lat.unit))
         if m_count is None:
-            m_count = int(math.ceil((xi0 + 8.0 * sigma) / lat.unit)) + 1
+            m_count = int(math.ceil((xi0 + 9.0 * sigma + GAUSS_MARGIN) / lat.unit)) - m_lo + 1
         m = np.arange(m_lo, m_lo + m_count, dtype=np.int64)
         xi = m.astype(np.float64) * lat.unit
         env = np.exp(-((xi - xi0) ** 2) / (2.0 * sigma * sigma))
@@ -230,6 +239,21 @@ def stress_case(psi_max: float = 0.01, num: int = 1 << 24, periods: float = 100.
     65536 cells, 3rd order by default."""
     return make_workload(f"stress psi={psi_max:g} P={num}", num, 150.0, 75, 65536,
                          periods, order, psi_max, 200.0, seed=5, theta=10.0 / 511.0)
+
+
+def pulse_case(a0: float, n_t: int = 75, order: int = 3, psi_max: float = 0.01, num: int = 1,
+               ncells: int = 1100) -> Workload:
+    """The paper's model problem (Sec. II): electrons at rest at x = 0, t = 0
+    hit by the Gaussian pulse a = a0 exp(-(xi - xi0)^2 / (2 sigma^2)) sin(xi),
+    xi = t - x, xi0 = 160 pi after the electrons' initial phase, sigma = 8 pi.
+    dt = 2 pi / n_t, dx = 1.01 dt.  The grid of ncells nodes starts eight
+    cells to the left of the electrons and is moved along with them; the run
+    lasts until the pulse has passed (steps = 0: decided by the driver)."""
+    lat = yee_lattice(n_t, j0=8 * 2 * 101)        # x_origin = -8 dx
+    return Workload(name=f"pulse a0={a0:g} T/dt={n_t} order {order} psi={psi_max:g}",
+                    num=num, a0=a0, n_t=n_t, ncells=ncells, steps=0, order=order,
+                    psi_max=psi_max, x0=np.zeros(num), p0=np.zeros((3, num)), lat=lat,
+                    kind="gauss")
 
 
 def batch_case(seed: int = 3, nruns: int = 64, periods: float = 50.0,

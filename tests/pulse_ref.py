@@ -1,0 +1,67 @@
+"""The FP64 oracle on the paper's model problem (Sec. II): electrons at rest
+hit by the Gaussian pulse of workloads.pulse_case, sampled from the same
+phase table the device uses.
+
+Two ways to run it:
+* whole: one grid long enough for the whole path (the oracle samples the
+  table node by node, so a long grid costs nothing), until the pulse has
+  passed (phase t - x beyond xi0 + 7 sigma), checked every `chunk` steps;
+* windows: the grids of a device run that moved its grid with the
+  electrons (runner.PulseRun.windows: start level, steps and shift of every
+  launch), so that every step sees the same nodes as on the device.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+from oracle import oracle as O
+from paper_2102_10983_amd import workloads as W
+
+XI_END = W.GAUSS_XI0 + 7.0 * W.GAUSS_SIGMA
+
+
+def _fields(wl, shift=0):
+    table, M, tshift = wl.table()
+    aE, bE, cE, aB, bB, cB = W.shifted_coeffs(wl.lat, tshift)
+    return O.FieldSource(table=table, M=M,
+                         coeffs=(aE, bE, cE + bE * shift, aB, bB, cB + bB * shift))
+
+
+def run_whole(wl, chunk: int = 20000, k_max: int = 12, max_steps: int = 1 << 28):
+    """Returns (state, counters, running max of |R - 1|, largest gamma)."""
+    fs = _fields(wl)
+    prm = O.make_params(2_000_000, wl.order, wl.dx, wl.dt, wl.psi_max, wl.x_origin, k_max=k_max)
+    st = O.State(wl.x0, *wl.p0)
+    r0 = O.dephasing_R(st.px, st.py, st.pz)
+    rmax = np.zeros(wl.num)
+    gmax = st.gamma().copy()
+    cnt = O.Counters()
+    n = 0
+    while n < max_steps:
+        O.push(prm, fs, st, n, chunk, counters=cnt, r0=r0, rmax=rmax, gmax=gmax)
+        n += chunk
+        live = st.status == 0
+        if not live.any() or np.all(n * wl.dt - st.x[live] > XI_END):
+            break
+    return st, cnt, rmax, gmax
+
+
+def run_windows(wl, windows, k_max: int = 12, forced_k=None):
+    """The oracle over the launches of a device run (n, steps, shift).
+    forced_k: optional [total steps, num] int8 array replacing the decision."""
+    st = O.State(wl.x0, *wl.p0)
+    r0 = O.dephasing_R(st.px, st.py, st.pz)
+    rmax = np.zeros(wl.num)
+    cnt = O.Counters()
+    ktrace = []
+    for n, steps, shift in windows:
+        prm = O.make_params(wl.ncells, wl.order, wl.dx, wl.dt, wl.psi_max,
+                            wl.x_origin + shift * wl.dx, k_max=k_max)
+        fk = None if forced_k is None else np.ascontiguousarray(forced_k[n:n + steps])
+        kt, pt = O.push(prm, _fields(wl, shift), st, n, steps, counters=cnt, r0=r0, rmax=rmax,
+                        trace=True, psi_trace=True, forced_k=fk)
+        ktrace.append((kt, pt))
+    kt = np.concatenate([k for k, _ in ktrace]) if ktrace else np.zeros((0, wl.num), np.int8)
+    pt = np.concatenate([p for _, p in ktrace]) if ktrace else np.zeros((0, wl.num))
+    return st, cnt, rmax, kt, pt

@@ -690,3 +690,31 @@ def test_energy_plane_wave_work_equals_energy_gain(orc):
     assert np.all(work > -1e-9)
     _, _, werr_nosub, _ = run(1e30)
     assert werr_sub.max() < 1e-2 * werr_nosub.max()
+
+
+def test_running_dephasing_and_peak_gamma_outputs(orc):
+    """The running maximum of |R - R0| / R0 (Eq. (R error)) and of gamma that
+    orc_push keeps equal the values taken after every single step."""
+    from paper_2102_10983_amd import workloads as W
+    wl = W.make_workload("pins", 64, 40.0, 75, 400, 2.0, 3, 0.01, 1.0, seed=77,
+                         theta=10.0 / 511.0)
+    table, M, shift = wl.table()
+    fs = orc.FieldSource(table=table, M=M, coeffs=W.shifted_coeffs(wl.lat, shift))
+    prm = orc.make_params(wl.ncells, 3, wl.dx, wl.dt, wl.psi_max, wl.x_origin)
+    a = orc.State(wl.x0, *wl.p0)
+    r0 = orc.dephasing_R(a.px, a.py, a.pz)
+    rmax = np.zeros(a.num)
+    gmax = np.zeros(a.num)
+    orc.push(prm, fs, a, 0, wl.steps, r0=r0, rmax=rmax, gmax=gmax)
+    b = orc.State(wl.x0, *wl.p0)
+    R0, rm, _, _, _ = orc.push_diagnostics(prm, fs, b, 0, wl.steps)
+    g = np.zeros(b.num)
+    c = orc.State(wl.x0, *wl.p0)
+    for n in range(wl.steps):
+        live = c.status == 0
+        orc.push(prm, fs, c, n, 1)
+        done = live & (c.status == 0)
+        gam = np.sqrt(1.0 + ((c.px * c.px + c.py * c.py) + c.pz * c.pz))
+        g = np.where(done, np.maximum(g, gam), g)
+    assert np.array_equal(R0, r0) and np.array_equal(rm, rmax)
+    assert np.array_equal(g, gmax) and rmax.max() > 0

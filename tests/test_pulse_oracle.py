@@ -1,0 +1,76 @@
+"""Paper-level pins of the oracle on the model problem of Sec. II: one
+electron at rest hit by the Gaussian pulse (xi0 = 160 pi after the
+electron's initial phase, sigma = 8 pi), prescribed fields ("perfectly
+propagating PIC"), c dt / dx = 1 / 1.01.  Each test checks a number or a
+trend the paper prints, with a loose bound: the paper's figure data are not
+available, its own runs differ in details it does not state, and the
+quantities are maxima along a trajectory.
+
+Not pinned (measured here, recorded in the design notes): the location of
+the maximum of chi^3 (the paper finds a0 ~ 25 at T/dt = 75; here the ratio
+is noisy and largest near a0 = 75) and a stopping point at t omega ~ 9110
+for a0 = 50, T/dt = 150 (here the nearest are at 8585 and 9483).
+"""
+
+import pytest
+
+from paper_2102_10983_amd import workloads as W
+from pulse_ref import run_whole
+
+
+def _run(a0, n_t, order, psi):
+    return run_whole(W.pulse_case(a0, n_t, order, psi))
+
+
+@pytest.mark.parametrize("a0", [5.0, 25.0, 50.0, 100.0])
+def test_third_order_with_subcycling_keeps_dephasing_below_a_tenth(a0):
+    """Sec. VI: with 3rd-order interpolation and sub-cycling (psi_max = 0.01)
+    at dt = lambda / 75 c, epsilon_dephasing stays below 0.1 for every
+    5 <= a0 <= 100; with 1st order it is far larger (Sec. IV)."""
+    _, _, r3, _ = _run(a0, 75, 3, 0.01)
+    _, _, r1, _ = _run(a0, 75, 1, 0.01)
+    assert r3[0] < 0.1
+    assert r1[0] > 10 * r3[0]          # "at least an order of magnitude" (Sec. I)
+
+
+def test_first_order_underestimates_the_peak_energy_threefold():
+    """Sec. IV: at a0 = 100 and dt = lambda / 75 c the 1st-order algorithm
+    reaches about a third of the analytic peak gamma = 1 + a0^2 / 2, with or
+    without sub-cycling; 3rd order with sub-cycling reaches it."""
+    g_th = 1.0 + 100.0 ** 2 / 2
+    for psi in (1e30, 0.01):
+        _, _, _, g = _run(100.0, 75, 1, psi)
+        assert 0.2 < g[0] / g_th < 0.45, (psi, g[0] / g_th)
+    _, _, _, g3 = _run(100.0, 75, 3, 0.01)
+    assert 0.9 < g3[0] / g_th < 1.1
+
+
+def test_tighter_psi_max_multiplies_subcycled_steps_about_twentyfold():
+    """Sec. V: at a0 = 50, dt = lambda / 150 c, 1st order, psi_max = 0.01
+    -> 0.001 takes the sub-cycled steps N* from about 72,000 to about
+    1.5e6, a factor of about 21."""
+    _, c1, _, _ = _run(50.0, 150, 1, 0.01)
+    _, c2, _, _ = _run(50.0, 150, 1, 0.001)
+    assert 5e4 < c1.n_star < 1e5, c1.n_star
+    assert 1e6 < c2.n_star < 2e6, c2.n_star
+    assert 14 < c2.n_star / c1.n_star < 28
+
+
+def test_subcycled_share_falls_as_a0_grows():
+    """Sec. VI: delta_steps = N* / (N* + N) decreases with a0 (the travel
+    time between stopping points grows), 3rd order, psi_max = 0.01,
+    dt = lambda / 75 c."""
+    ds = []
+    for a0 in (10.0, 25.0, 50.0, 100.0):
+        _, c, _, _ = _run(a0, 75, 3, 0.01)
+        ds.append(c.n_star / (c.n_star + c.steps))
+    assert all(a > b for a, b in zip(ds, ds[1:])), ds
+
+
+@pytest.mark.parametrize("a0", [5.0, 25.0, 50.0, 100.0])
+def test_standard_algorithm_needs_dt_lambda_over_600(a0):
+    """Sec. VI: the standard algorithm (1st order, no sub-cycling) needs
+    dt = lambda / 600 c to match the new algorithm at lambda / 75 c:
+    epsilon_dephasing below 0.1 there for 5 <= a0 <= 100."""
+    _, _, r, _ = _run(a0, 600, 1, 1e30)
+    assert r[0] < 0.1
