@@ -188,6 +188,31 @@ __device__ __forceinline__ void window_to_monomial(double *sw, int nn, int lane)
     }
 }
 
+// The same for a node read straight from the ring (a group too wide for a
+// window): the coefficients are formed with the operations of
+// window_to_monomial, so the value does not depend on which path the
+// particle's group takes.
+template <int P>
+__device__ __forceinline__ double horner_ring(gdptr ring, const int32_t (&off)[P + 1], int i,
+                                              int field, double u)
+{
+    double F[P + 1];
+#pragma unroll
+    for (int j = 0; j <= P; ++j) F[j] = ring[off[j] + i];
+    double a[P + 1];
+#pragma unroll
+    for (int m = 0; m <= P; ++m) {
+        double v = mono_c<P>(field, m, 0) * F[0];
+#pragma unroll
+        for (int j = 1; j <= P; ++j) v = fma(mono_c<P>(field, m, j), F[j], v);
+        a[m] = v;
+    }
+    double v = a[P];
+#pragma unroll
+    for (int m = P - 1; m >= 0; --m) v = fma(v, u, a[m]);
+    return v;
+}
+
 // N(u) of one node from its coefficient column (rows 2m + field).
 template <int P>
 __device__ __forceinline__ double horner_lds(const double *p, int field, double u)
@@ -209,7 +234,6 @@ __global__ void __launch_bounds__(64 * WPG)
 {
     constexpr int ROWS = 2 * (P + 1);                 // row 2j: E of level j, 2j+1: B
     constexpr int NPF = (ROWS * PF_NW + 63) / 64;     // window values per lane
-    constexpr int STRIDE = 2 * (P + 1);               // weight-table entry
     static_assert(PF_NW == 16, "the step-ahead load maps lane bits 4, 5 to field, level");
     __shared__ double sw_all[WPG][ROWS * WWIN];
     __shared__ uint32_t shist_all[WPG][PIC_K_MAX_LIMIT + 1];   // completed steps per k > 0
@@ -470,10 +494,9 @@ __global__ void __launch_bounds__(64 * WPG)
                 const double dt_new = dt * fnew;
                 const int nsub = 1 << (2 * k);
                 const double cn = 0.5 * qm * dt_new;
-                const double *Wk = a.wtab + wtab_offset(k) * STRIDE;
                 double u = 0.0;                                // s - 1/2 of sub-step j
                 done = true;
-                for (int j = 1; j <= nsub; ++j, Wk += STRIDE, u += fnew) {
+                for (int j = 1; j <= nsub; ++j, u += fnew) {
                     if (j > 1 && !(x >= 0.5 && x < ncm1)) {
                         done = false;
                         break;
@@ -492,10 +515,10 @@ __global__ void __launch_bounds__(64 * WPG)
                         e0 = horner_lds<P>(pe, 0, u);
                         e1 = horner_lds<P>(pe + 1, 0, u);
                     } else {
-                        bb0 = comb_fma<P>(ringB, lv.off, ib, Wk + P + 1);
-                        bb1 = comb_fma<P>(ringB, lv.off, ib + 1, Wk + P + 1);
-                        e0 = comb_fma<P>(ringE, lv.off, ie, Wk);
-                        e1 = comb_fma<P>(ringE, lv.off, ie + 1, Wk);
+                        bb0 = horner_ring<P>(ringB, lv.off, ib, 1, u);
+                        bb1 = horner_ring<P>(ringB, lv.off, ib + 1, 1, u);
+                        e0 = horner_ring<P>(ringE, lv.off, ie, 0, u);
+                        e1 = horner_ring<P>(ringE, lv.off, ie + 1, 0, u);
                     }
                     const double Es = tent_fma(uE - fe, e0, e1);
                     const double vb = deph ? py * ig : 0.0;
