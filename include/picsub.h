@@ -261,6 +261,17 @@ pic_status pic_strict_set(pic_ctx *ctx, int32_t on);
 pic_status pic_diag_noalloc(pic_ctx *ctx, double *gamma, double *px, double *py, double *pz,
                             double *x, int8_t *k_last, uint8_t *status, pic_counters *cnt);
 
+/* Move the grid of one run by `cells` nodes (positive: towards +x), for
+ * particles that travel farther than a grid can hold (an electron riding a
+ * pulse crosses ~10^6 cells, Sec. II): the run's x_origin becomes
+ * x_origin0 + shift * dx in FP64, x_origin0 being the origin at creation and
+ * shift the sum of all moves (written to *x_origin if not NULL).  Particle
+ * positions are absolute and do not change; every ring level of the run is
+ * dropped (load the levels the next push needs for the new nodes, e.g.
+ * with lattice coefficients c + b * shift).  Not for runs in device-driven
+ * mode (PIC_E_STATE).  Synchronises the stream. */
+pic_status pic_grid_shift(pic_ctx *ctx, int32_t run, int64_t cells, double *x_origin);
+
 /* Reset the counters to zero (asynchronous). */
 pic_status pic_counters_reset(pic_ctx *ctx);
 

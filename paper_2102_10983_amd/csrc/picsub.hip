@@ -58,6 +58,8 @@ struct RunHost {
     int64_t M = 0, co[6] = {0, 0, 0, 0, 0, 0};
     int64_t n_dev = 0;           // level the device-driven counter reaches after queued work
     int64_t n_stop = INT64_MAX;  // device-driven stop level
+    double x_origin0 = 0.0;      // x_origin at creation; the grid sits shift cells from it
+    int64_t shift = 0;
 };
 
 // Staging area of pic_diag_noalloc: a layout of [counter sums: NCNT words,
@@ -547,6 +549,7 @@ pic_status pic_batch_create(const pic_params *per_run, const int64_t *np, int32_
     for (int r = 0; r < nruns; ++r) {
         RunHost &R = ctx->runs[size_t(r)];
         R.prm = per_run[r];
+        R.x_origin0 = R.prm.x_origin;
         R.np = np[r];
         R.caller_off = caller;
         R.p_off = slot;
@@ -1013,6 +1016,21 @@ pic_status pic_push_subcycled(pic_ctx *ctx, int64_t n, int32_t S)
     const pic_status st = predictor_turn(ctx, n);
     if (st) return st;
     return launch_push(ctx, n, S, ctx->stream);
+}
+
+pic_status pic_grid_shift(pic_ctx *ctx, int32_t run, int64_t cells, double *x_origin)
+{
+    CTX_CHECK(ctx);
+    if (run < 0 || run >= ctx->nruns) return fail(ctx, PIC_E_ARG, "bad run %d", run);
+    RunHost &R = ctx->runs[size_t(run)];
+    if (R.driven) return fail(ctx, PIC_E_STATE, "run %d is in device-driven mode", run);
+    if (cells > (int64_t(1) << 40) || cells < -(int64_t(1) << 40))
+        return fail(ctx, PIC_E_ARG, "shift out of range");
+    R.shift += cells;
+    R.prm.x_origin = R.x_origin0 + double(R.shift) * R.prm.dx;
+    std::fill(R.tags.begin(), R.tags.end(), NO_LEVEL);
+    if (x_origin) *x_origin = R.prm.x_origin;
+    return upload_desc(ctx, run);
 }
 
 pic_status pic_strict_set(pic_ctx *ctx, int32_t on)

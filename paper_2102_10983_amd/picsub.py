@@ -27,6 +27,7 @@ MEM_HOST, MEM_DEVICE = 0, 1
 EXPORTS = ("pic_create", "pic_destroy", "pic_last_error", "pic_particles_set",
            "pic_fields_load", "pic_fields_load_lattice", "pic_push_subcycled",
            "pic_ktrace_set", "pic_diag", "pic_diag_noalloc", "pic_diag_r", "pic_strict_set",
+           "pic_grid_shift",
            "pic_counters_reset",
            "pic_batch_create",
            "pic_fields_load_r", "pic_fields_load_lattice_r", "pic_source_set", "pic_advance",
@@ -109,6 +110,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "pic_diag_r": ([vp, i32, C.c_int, vp, vp, vp, vp, vp, vp, vp, C.POINTER(Counters)],
                        C.c_int),
         "pic_strict_set": ([vp, i32], C.c_int),
+        "pic_grid_shift": ([vp, i32, i64, C.POINTER(dbl)], C.c_int),
         "pic_counters_reset": ([vp], C.c_int),
         "pic_batch_create": ([vp, vp, i32, vp, C.POINTER(vp)], C.c_int),
         "pic_fields_load_r": ([vp, i32, i64, C.c_int, vp, vp], C.c_int),
@@ -516,6 +518,13 @@ class Pusher:
             out["k_last"].ctypes.data, out["status"].ctypes.data, C.byref(c)))
         out["counters"] = c.as_dict()
         return out
+
+    def grid_shift(self, cells: int, run: int = 0) -> float:
+        """pic_grid_shift: move the run's grid by `cells` nodes; returns the
+        new x_origin."""
+        xo = C.c_double(0.0)
+        self._check(self._lib.pic_grid_shift(self._ctx, int(run), int(cells), C.byref(xo)))
+        return xo.value
 
     def strict_set(self, on: bool = True):
         self._check(self._lib.pic_strict_set(self._ctx, 1 if on else 0))

@@ -65,3 +65,23 @@ def run_windows(wl, windows, k_max: int = 12, forced_k=None):
     kt = np.concatenate([k for k, _ in ktrace]) if ktrace else np.zeros((0, wl.num), np.int8)
     pt = np.concatenate([p for _, p in ktrace]) if ktrace else np.zeros((0, wl.num))
     return st, cnt, rmax, kt, pt
+
+
+def moving_windows(wl, S: int = 1000, left: int = 8, k_max: int = 12):
+    """The launches a moving-grid run makes (the rule of runner.PulseRun:
+    before each launch the grid is shifted so the electron sits `left`
+    cells from node 0), found with the oracle itself; returns the windows."""
+    st = O.State(wl.x0, *wl.p0)
+    windows = []
+    n = 0
+    while True:
+        live = st.status == 0
+        if not live.any() or np.all(n * wl.dt - st.x[live] > XI_END):
+            break
+        shift = int(np.floor((st.x[live].min() - wl.x_origin) / wl.dx)) - left
+        prm = O.make_params(wl.ncells, wl.order, wl.dx, wl.dt, wl.psi_max,
+                            wl.x_origin + shift * wl.dx, k_max=k_max)
+        O.push(prm, _fields(wl, shift), st, n, S)
+        windows.append((n, S, shift))
+        n += S
+    return windows
