@@ -20,11 +20,12 @@
 // 1/gamma from v_rsq_f64 and the Boris denominator from v_rcp_f64, each
 // refined by one Newton step; x is carried in node units.  p_z never
 // changes in this geometry (E along y, B along z), so 1 + p_z^2 is a
-// constant of each lane.  When a wavefront sub-cycles, its LDS window is
-// rewritten once per step as the coefficients of each node's interpolating
-// polynomial in u = s - 1/2 (the same polynomial as the Lagrange form), so a
-// sub-step evaluates it by Horner's rule at u = (j - 1) / 4^k instead of
-// loading the weights of (k, j).  Completed sub-cycled steps are counted per
+// constant of each lane.  At orders 1 and 3, when a wavefront sub-cycles, its
+// LDS window is rewritten once per step as the coefficients of each node's
+// interpolating polynomial in u = s - 1/2 (the same polynomial as the
+// Lagrange form), so a sub-step evaluates it by Horner's rule at
+// u = (j - 1) / 4^k instead of loading the weights of (k, j); order 5 keeps
+// the weights.  Completed sub-cycled steps are counted per
 // k in the wavefront's LDS, one distinct k at a time.
 #pragma once
 
@@ -168,23 +169,30 @@ __device__ constexpr double mono_c(int field, int m, int j)
 
 // Replace the level rows of the LDS window (row 2j: E of level j, 2j + 1: B,
 // nodes 0 .. nn - 1) by the monomial coefficients (row 2m: a_m of E, 2m + 1:
-// of B), one node and field per lane.
+// of B), one node per lane, both fields (the field is then known at compile
+// time, so every entry of C is a constant operand rather than a per-lane
+// selection the compiler may keep in registers across the step loop).
+template <int P, int FIELD>
+__device__ __forceinline__ void column_to_monomial(double *col)
+{
+    double F[P + 1];
+#pragma unroll
+    for (int j = 0; j <= P; ++j) F[j] = col[2 * j * WWIN];
+#pragma unroll
+    for (int m = 0; m <= P; ++m) {
+        double v = mono_c<P>(FIELD, m, 0) * F[0];
+#pragma unroll
+        for (int j = 1; j <= P; ++j) v = fma(mono_c<P>(FIELD, m, j), F[j], v);
+        col[2 * m * WWIN] = v;
+    }
+}
+
 template <int P>
 __device__ __forceinline__ void window_to_monomial(double *sw, int nn, int lane)
 {
-    for (int c = lane; c < 2 * nn; c += 64) {
-        const int f = c >= nn ? 1 : 0;
-        double *col = sw + f * WWIN + (c - f * nn);
-        double F[P + 1];
-#pragma unroll
-        for (int j = 0; j <= P; ++j) F[j] = col[2 * j * WWIN];
-#pragma unroll
-        for (int m = 0; m <= P; ++m) {
-            double v = mono_c<P>(f, m, 0) * F[0];
-#pragma unroll
-            for (int j = 1; j <= P; ++j) v = fma(mono_c<P>(f, m, j), F[j], v);
-            col[2 * m * WWIN] = v;
-        }
+    for (int c = lane; c < nn; c += 64) {
+        column_to_monomial<P, 0>(sw + c);
+        column_to_monomial<P, 1>(sw + WWIN + c);
     }
 }
 
@@ -199,17 +207,17 @@ __device__ __forceinline__ double horner_ring(gdptr ring, const int32_t (&off)[P
     double F[P + 1];
 #pragma unroll
     for (int j = 0; j <= P; ++j) F[j] = ring[off[j] + i];
-    double a[P + 1];
+    // each coefficient is formed just before Horner's rule takes it (the
+    // same operations; fewer values live at once)
+    auto coeff = [&](int m) {
+        double c = mono_c<P>(field, m, 0) * F[0];
 #pragma unroll
-    for (int m = 0; m <= P; ++m) {
-        double v = mono_c<P>(field, m, 0) * F[0];
+        for (int j = 1; j <= P; ++j) c = fma(mono_c<P>(field, m, j), F[j], c);
+        return c;
+    };
+    double v = coeff(P);
 #pragma unroll
-        for (int j = 1; j <= P; ++j) v = fma(mono_c<P>(field, m, j), F[j], v);
-        a[m] = v;
-    }
-    double v = a[P];
-#pragma unroll
-    for (int m = P - 1; m >= 0; --m) v = fma(v, u, a[m]);
+    for (int m = P - 1; m >= 0; --m) v = fma(v, u, coeff(m));
     return v;
 }
 
@@ -234,6 +242,12 @@ __global__ void __launch_bounds__(64 * WPG)
 {
     constexpr int ROWS = 2 * (P + 1);                 // row 2j: E of level j, 2j+1: B
     constexpr int NPF = (ROWS * PF_NW + 63) / 64;     // window values per lane
+    // Sub-steps evaluate each node's polynomial by Horner's rule from
+    // coefficients formed once per sub-cycled step (orders 1, 3), or weight the
+    // window's levels with the (k, j) entry of the weight table (order 5, where
+    // forming 2 (P + 1)^2 products per node costs more than it saves).
+    constexpr bool MONO = P <= 3;
+    constexpr int STRIDE = 2 * (P + 1);               // weight-table entry
     static_assert(PF_NW == 16, "the step-ahead load maps lane bits 4, 5 to field, level");
     __shared__ double sw_all[WPG][ROWS * WWIN];
     __shared__ uint32_t shist_all[WPG][PIC_K_MAX_LIMIT + 1];   // completed steps per k > 0
@@ -358,9 +372,12 @@ __global__ void __launch_bounds__(64 * WPG)
 
         // Step-ahead loads: the levels of step n+1 on the nodes any lane can
         // reach from this step's cells (all within rad of cref).
-        const bool pf_next = st + 1 < S_run && rad >= 0 &&
+        const bool pf_next = st + 1 < S_run && rad >= 0 && ncells >= PF_NW &&
                              (lmask & ~(wballot(cell >= cref - rad) & wballot(cell <= cref + rad))) == 0;
-        const int nlo = cref - rad - margin - 1;
+        // first node of the window, kept inside the grid on the scalar unit
+        // (near an end the window may then miss a lane, which the coverage
+        // check of the next step sends to direct gathers of the same values)
+        const int nlo = min(max(cref - rad - margin - 1, 0), ncells - PF_NW);
         double pf[NPF];
         if (pf_next) {
 #pragma unroll
@@ -368,7 +385,7 @@ __global__ void __launch_bounds__(64 * WPG)
                 // value e = lane + 64 h: row e / 16 (level e / 32, field
                 // (e / 16) & 1), node nlo + e % 16
                 if (lane + 64 * h < ROWS * PF_NW) {
-                    const int node = min(max(nlo + pf_q, 0), ncells - 1);
+                    const int node = nlo + pf_q;
                     const int32_t o_even = lvo[2 * h + 1], o_odd = lvo[2 * h + 2];
                     const int32_t off = pf_hi ? o_odd : o_even;
                     pf[h] = pf_src[off + node];
@@ -424,16 +441,15 @@ __global__ void __launch_bounds__(64 * WPG)
             const double uE = x - 0.5;
             const double flE = floor(uE);
             const int iE = int(flE);
-            double e0, e1;
+            // the tent is taken inside each branch, so the window path does
+            // not wait for the rare branch's loads (nor for the step-ahead
+            // loads in flight) where the branches meet
             if (use_win) {
                 const double *p = sw + (2 * P) * WWIN + (iE - wlo);
-                e0 = p[0];
-                e1 = p[1];
+                Ek = tent_fma(uE - flE, p[0], p[1]);
             } else {
-                e0 = ringE[lv.off[P] + iE];
-                e1 = ringE[lv.off[P] + iE + 1];
+                Ek = tent_fma(uE - flE, ringE[lv.off[P] + iE], ringE[lv.off[P] + iE + 1]);
             }
-            Ek = tent_fma(uE - flE, e0, e1);
         }
 
         // A sub-cycled step outside the step-ahead window stages its own.
@@ -461,7 +477,7 @@ __global__ void __launch_bounds__(64 * WPG)
             }
         }
         // sub-steps read the window's nodes as polynomials in u
-        if (lds && hmask) {
+        if (MONO && lds && hmask) {
             wave_lds_sync();
             window_to_monomial<P>(sw, nwin, lane);
             wave_lds_sync();
@@ -495,6 +511,7 @@ __global__ void __launch_bounds__(64 * WPG)
                 const int nsub = 1 << (2 * k);
                 const double cn = 0.5 * qm * dt_new;
                 double u = 0.0;                                // s - 1/2 of sub-step j
+                const double *Wk = MONO ? nullptr : a.wtab + wtab_offset(k) * STRIDE;
                 done = true;
                 for (int j = 1; j <= nsub; ++j, u += fnew) {
                     if (j > 1 && !(x >= 0.5 && x < ncm1)) {
@@ -507,18 +524,35 @@ __global__ void __launch_bounds__(64 * WPG)
                     const double fe = floor(uE);
                     const int ie = int(fe);
                     double bb0, bb1, e0, e1;
-                    if (lds) {
-                        const double *pb = sw + (ib - base);
-                        const double *pe = sw + (ie - base);
-                        bb0 = horner_lds<P>(pb, 1, u);
-                        bb1 = horner_lds<P>(pb + 1, 1, u);
-                        e0 = horner_lds<P>(pe, 0, u);
-                        e1 = horner_lds<P>(pe + 1, 0, u);
+                    if constexpr (MONO) {
+                        if (lds) {
+                            const double *pb = sw + (ib - base);
+                            const double *pe = sw + (ie - base);
+                            bb0 = horner_lds<P>(pb, 1, u);
+                            bb1 = horner_lds<P>(pb + 1, 1, u);
+                            e0 = horner_lds<P>(pe, 0, u);
+                            e1 = horner_lds<P>(pe + 1, 0, u);
+                        } else {
+                            bb0 = horner_ring<P>(ringB, lv.off, ib, 1, u);
+                            bb1 = horner_ring<P>(ringB, lv.off, ib + 1, 1, u);
+                            e0 = horner_ring<P>(ringE, lv.off, ie, 0, u);
+                            e1 = horner_ring<P>(ringE, lv.off, ie + 1, 0, u);
+                        }
                     } else {
-                        bb0 = horner_ring<P>(ringB, lv.off, ib, 1, u);
-                        bb1 = horner_ring<P>(ringB, lv.off, ib + 1, 1, u);
-                        e0 = horner_ring<P>(ringE, lv.off, ie, 0, u);
-                        e1 = horner_ring<P>(ringE, lv.off, ie + 1, 0, u);
+                        const double *W = Wk + (j - 1) * STRIDE;   // weights of (k, j)
+                        if (lds) {
+                            const double *pb = sw + (ib - base);
+                            const double *pe = sw + (ie - base);
+                            bb0 = comb_lds<P>(pb, 1, W + P + 1);
+                            bb1 = comb_lds<P>(pb + 1, 1, W + P + 1);
+                            e0 = comb_lds<P>(pe, 0, W);
+                            e1 = comb_lds<P>(pe + 1, 0, W);
+                        } else {
+                            bb0 = comb_fma<P>(ringB, lv.off, ib, W + P + 1);
+                            bb1 = comb_fma<P>(ringB, lv.off, ib + 1, W + P + 1);
+                            e0 = comb_fma<P>(ringE, lv.off, ie, W);
+                            e1 = comb_fma<P>(ringE, lv.off, ie + 1, W);
+                        }
                     }
                     const double Es = tent_fma(uE - fe, e0, e1);
                     const double vb = deph ? py * ig : 0.0;
