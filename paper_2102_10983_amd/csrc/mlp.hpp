@@ -1,7 +1,7 @@
 // mlp.hpp -- the sub-cycling load predictor: features, forward, gradients,
 // Adam.
 //
-// Network: 8 -> 64 -> 64 -> 1, GELU (erf form) after both hidden layers,
+// Network: 8 -> 64 -> 64 -> 1, GELU (erf form, erf to 1.5e-7) after both hidden layers,
 // weights used in BF16 (rounded to nearest even from FP32 master weights),
 // activations and accumulation in FP32.  Parameter vector (FP32, 4801
 // entries): W1[64][8], b1[64], W2[64][64], b2[64], W3[64], b3.
@@ -34,15 +34,32 @@ __host__ __device__ inline float bf16_value(uint16_t b)
     return f;
 }
 
+// erf by Abramowitz & Stegun's rational approximation 7.1.26 (Handbook of
+// Mathematical Functions, 1964): erf(x) = 1 - t (a1 + t (a2 + t (a3 +
+// t (a4 + t a5)))) exp(-x^2), t = 1 / (1 + p x) for x >= 0, odd in x;
+// absolute error at most 1.5e-7 (one or two FP32 ulps of values near 1).
+// Branch-free: hardware reciprocal and exponential estimates.
+__device__ __forceinline__ float erf_as(float x)
+{
+    const float ax = fabsf(x);
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, ax, 1.0f));
+    float q = fmaf(1.061405429f, t, -1.453152027f);
+    q = fmaf(q, t, 1.421413741f);
+    q = fmaf(q, t, -0.284496736f);
+    q = fmaf(q, t, 0.254829592f);
+    const float e = __builtin_amdgcn_exp2f(-(ax * ax) * 1.44269504088896341f);
+    return copysignf(fmaf(-(q * t), e, 1.0f), x);
+}
+
 __device__ __forceinline__ float gelu(float z)
 {
-    return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f));
+    return 0.5f * z * (1.0f + erf_as(z * 0.70710678118654752f));
 }
 
 __device__ __forceinline__ float gelu_grad(float z)
 {
-    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) +
-           z * 0.39894228040143268f * expf(-0.5f * z * z);
+    return 0.5f * (1.0f + erf_as(z * 0.70710678118654752f)) +
+           z * 0.39894228040143268f * __builtin_amdgcn_exp2f(-0.5f * z * z * 1.44269504088896341f);
 }
 
 // Stage the BF16-valued weights in LDS as FP32; from FP32 masters (w32)
@@ -54,28 +71,22 @@ __device__ __forceinline__ void stage_weights(float *sw, const float *w32, const
     __syncthreads();
 }
 
-// One sample through the network (lane = sample): hidden-1 neurons one
-// at a time, each scattered into the 64 layer-2 accumulators.
-__device__ __forceinline__ float mlp_forward_one(const float *__restrict__ sw, const float (&u)[NF])
-{
-    float z2[NH];
-#pragma unroll
-    for (int o = 0; o < NH; ++o) z2[o] = sw[OFF_B2 + o];
-#pragma unroll 1
-    for (int i = 0; i < NH; ++i) {
-        float z = sw[OFF_B1 + i];
-#pragma unroll
-        for (int j = 0; j < NF; ++j) z = fmaf(sw[OFF_W1 + i * NF + j], u[j], z);
-        const float h = gelu(z);
-#pragma unroll
-        for (int o = 0; o < NH; ++o) z2[o] = fmaf(sw[OFF_W2 + o * NH + i], h, z2[o]);
-    }
-    float y = sw[OFF_B3];
-#pragma unroll
-    for (int o = 0; o < NH; ++o) y = fmaf(sw[OFF_W3 + o], gelu(z2[o]), y);
-    return y;
-}
+typedef float floatx16 __attribute__((ext_vector_type(16)));
 
+// Forward pass with the second layer (64 x 64 per sample, 88 % of the
+// network's multiply-adds) on the matrix cores, FP32 in and out
+// (v_mfma_f32_32x32x2_f32: D[32 x 32] += A[32 x 2] B[2 x 32]), so the
+// arithmetic is the network's own: BF16-valued weights, FP32 activations
+// and sums (summed in the matrix unit's order).  A wavefront takes 64
+// samples at a time and computes Z2^T = W2 H1^T as 2 x 2 tiles of 32 x 32
+// over 32 steps of K = 2.  In step kk lane l (c = l mod 32, h = l / 32)
+// supplies
+//   A: W2[32 mt + c][2 kk + h] (from LDS),
+//   B: H1[32 nt + c][2 kk + h], the first layer of samples c and 32 + c at
+//      hidden neuron 2 kk + h, which it computes just before,
+// and it ends holding D: Z2[sample 32 nt + c][output 32 mt + 8 (r / 4) +
+// 4 h + r mod 4], so a sample's output sum is the lane's own 32 terms plus
+// those of lane l ^ 32.
 __global__ void __launch_bounds__(256) mlp_forward_kernel(const uint16_t *__restrict__ w16,
                                                           const float *__restrict__ norm,
                                                           const float *__restrict__ feat,
@@ -83,12 +94,60 @@ __global__ void __launch_bounds__(256) mlp_forward_kernel(const uint16_t *__rest
 {
     __shared__ float sw[NPARAM];
     stage_weights(sw, nullptr, w16);
-    for (int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; s < n;
-         s += int64_t(gridDim.x) * blockDim.x) {
-        float u[NF];
+    const int lane = threadIdx.x & 63;
+    const int c = lane & 31, h = lane >> 5;
+    const int64_t wave = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = (int64_t(gridDim.x) * blockDim.x) >> 6;
+    for (int64_t base = wave * 64; base < n; base += nwaves * 64) {
+        float u[2][NF];
 #pragma unroll
-        for (int j = 0; j < NF; ++j) u[j] = (feat[s * NF + j] - norm[j]) * norm[NF + j];
-        out[s] = mlp_forward_one(sw, u);
+        for (int nt = 0; nt < 2; ++nt) {
+            const int64_t s = base + 32 * nt + c;
+#pragma unroll
+            for (int j = 0; j < NF; ++j)
+                u[nt][j] = s < n ? (feat[s * NF + j] - norm[j]) * norm[NF + j] : 0.f;
+        }
+        floatx16 acc[2][2];
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[mt][nt][r] = 0.f;
+#pragma unroll 1
+        for (int kk = 0; kk < NH / 2; ++kk) {
+            const int i = 2 * kk + h;
+            float hb[2];
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) {
+                float z = sw[OFF_B1 + i];
+#pragma unroll
+                for (int j = 0; j < NF; ++j) z = fmaf(sw[OFF_W1 + i * NF + j], u[nt][j], z);
+                hb[nt] = gelu(z);
+            }
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt) {
+                const float a = sw[OFF_W2 + (32 * mt + c) * NH + i];
+#pragma unroll
+                for (int nt = 0; nt < 2; ++nt)
+                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, hb[nt], acc[mt][nt], 0, 0, 0);
+            }
+        }
+        // bias, GELU and the output neuron
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) {
+            float y = 0.f;
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int o = 32 * mt + 8 * (r >> 2) + 4 * h + (r & 3);
+                    y = fmaf(sw[OFF_W3 + o], gelu(acc[mt][nt][r] + sw[OFF_B2 + o]), y);
+                }
+            y += __shfl_xor(y, 32);
+            const int64_t s = base + 32 * nt + c;
+            if (h == 0 && s < n) out[s] = y + sw[OFF_B3];
+        }
     }
 }
 
