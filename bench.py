@@ -188,9 +188,10 @@ class Pass:
     windows of S steps, each run stopping at its own step count)."""
 
     def __init__(self, wl, S, precision, binning, predictor=None, fields="lattice",
-                 occupancy=0):
+                 occupancy=0, graph=False):
         from paper_2102_10983_amd import runner
         self.wl = wl
+        self.graph = graph
         self.fill_events = []
         self.S = S
         self.binning = binning
@@ -209,6 +210,12 @@ class Pass:
             self.a0 = wl.a0
         if occupancy:
             self.pusher.tune_set(occupancy=occupancy)
+        if graph:
+            # a batch's whole pass (every window of every run) recorded once
+            # as a HIP graph; each step replays it
+            assert self.batch
+            self.run.reset()
+            self.run.capture()
 
     def step(self, stream=None, events=None):
         import torch
@@ -222,6 +229,17 @@ class Pass:
             from paper_2102_10983_amd import predictor as PR
             score = PR.psi_score(self.pusher, self.a0, wl.dt, wl.psi_max, n=0)
             self.pusher.prebin(score, nbuckets=1, width=self.pb_width)
+        if self.batch and self.graph:
+            if events is not None:
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                run.replay()
+                e1.record(stream)
+                events.append((e0, e1))
+            else:
+                run.replay()
+            return
         if self.batch:
             for _ in range(run.windows):
                 if events is not None:
@@ -268,6 +286,8 @@ class Pass:
         return time.perf_counter() - t0
 
     def close(self):
+        if self.graph:
+            self.pusher.graph_release()
         self.run.close()
 
 
@@ -439,6 +459,8 @@ def main():
 
     compare = []
     if not args.no_compare:
+        # label, workload, precision, binning, fields, timed steps[, steps per
+        # launch, graph]
         legs = [("plain binning, same precision", args.workload, args.precision, "none",
                  args.fields, args.steps),
                 ("groups ordered by the step-0 Psi criterion (non-learned control), same "
@@ -463,7 +485,14 @@ def main():
                                      "none", "lattice", 1))
                         legs.append((f"workload {name}, step-0 Psi order", name,
                                      args.precision, "psi", "lattice", 1))
-        for label, wname, prec, binning, fields, nsteps in legs:
+                    if name == "batch":
+                        legs.append(("workload batch in device-driven windows of 750 steps, "
+                                     "the whole pass replayed from one HIP graph (rings of 753 "
+                                     "levels instead of every level of a run)", name,
+                                     args.precision, args.binning, "lattice", 1, 750, True))
+        for leg_spec in legs:
+            label, wname, prec, binning, fields, nsteps = leg_spec[:6]
+            leg_S, leg_graph = (leg_spec[6], leg_spec[7]) if len(leg_spec) > 6 else (0, False)
             if (wname == args.workload and prec == args.precision and binning == args.binning
                     and fields == args.fields):
                 continue
@@ -471,15 +500,16 @@ def main():
                 continue
             lwl, ldesc = (wl, wdesc) if wname == args.workload else make_workload(wname, args)
             lsteps = max(w.steps for w in lwl) if isinstance(lwl, list) else lwl.steps
-            p = Pass(lwl, lsteps if args.S <= 0 else args.S, prec, binning,
+            p = Pass(lwl, leg_S or (lsteps if args.S <= 0 else args.S), prec, binning,
                      model if binning == "learned" else None, fields,
-                     occupancy if prec == "fp64fast" else 0)
+                     occupancy if prec == "fp64fast" else 0, graph=leg_graph)
             p.pb_width = args.pb_width
             ev = []
             t = p.time(nsteps, 1, stream, ev)
             c = p.pusher.counters()
             leg = {"label": label, "workload": ldesc if wname != args.workload else args.workload,
                    "precision": prec, "binning": binning, "fields": fields,
+                   **({"steps_per_launch": leg_S, "hip_graph": True} if leg_graph else {}),
                    "steps": nsteps, "ms_per_step": t / nsteps * 1e3,
                    "value": c["sub_steps"] * nsteps / t,
                    "push_ms": sum(a.elapsed_time(b) for a, b in ev) / nsteps,

@@ -507,8 +507,9 @@ pic_status pic_mlp_adam(float *w, float *m, float *v, const float *grad, int32_t
  * width (groups within one step keep their slot order, which keeps
  * co-running groups close in space), and the prio_groups heaviest issue
  * at raised priority.  Particles stay in their run;
- * results are unchanged.  Not allowed while a graph is captured
- * (PIC_E_STATE).  Synchronous. */
+ * results are unchanged.  Allowed while a graph is captured: the particle
+ * arrays, the group order and the priorities are rewritten in place, so
+ * the graph's next replay runs in the new order.  Synchronous. */
 pic_status pic_prebin(pic_ctx *ctx, const float *score, int32_t nbuckets, float width,
                       int32_t prio_groups);
 

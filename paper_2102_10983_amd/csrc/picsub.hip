@@ -1589,7 +1589,9 @@ pic_status pic_prebin(pic_ctx *ctx, const float *score, int32_t nbuckets, float 
     if (!score && ctx->np > 0) return fail(ctx, PIC_E_ARG, "null score");
     if (nbuckets < 1 || nbuckets > 64 || !(width > 0) || prio_groups < 0)
         return fail(ctx, PIC_E_ARG, "need 1..64 buckets, width > 0, prio_groups >= 0");
-    if (ctx->gexec) return fail(ctx, PIC_E_STATE, "release the captured graph before re-binning");
+    // a captured graph may stay: the particle arrays, the group order and
+    // the priorities are rewritten in place (the launches it recorded hold
+    // the same pointers), so its next replay runs in the new order
     if (ctx->np == 0) return PIC_OK;
     const int64_t slots = ctx->slots;
     const size_t n = size_t(slots);
