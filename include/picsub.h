@@ -349,9 +349,14 @@ pic_status pic_run_counters(pic_ctx *ctx, int32_t run, pic_counters *cnt);
  * (v_before + v_after), summed from the start, and the largest
  * |(gamma_end - gamma_start) - work| over a single completed step (kinetic
  * energy in m c^2; the paper normalises it by |q| E0 dt).
+ *
+ * Peak energy (Sec. IV, Eq. (theoretical gamma)): the running maximum of
+ * gamma after each completed step, to set against the analytic peak
+ * 1 + a0^2 / 2 of an electron starting at rest.
  * ------------------------------------------------------------------ */
 
-/* on = 1: (re)start: R0 := R of every particle now, maxima and work := 0;
+/* on = 1: (re)start: R0 := R of every particle now, the gamma maximum :=
+ * gamma now, the other maxima and the work := 0;
  * from then on every push kernel updates them after each completed step
  * of a live particle (a few square roots and divisions per sub-step, IEEE
  * in the PIC_FP64 kernels, bit-identical to a CPU loop).  on = 0: stop
@@ -373,6 +378,10 @@ pic_status pic_dephasing_read(pic_ctx *ctx, pic_mem mem, double *R0,
  * mismatch of every particle, as pic_dephasing_read. */
 pic_status pic_energy_read(pic_ctx *ctx, pic_mem mem, double *work,
                            double *err_max);
+
+/* The largest gamma of every particle since the diagnostics were (re)started
+ * (np doubles, caller order), as pic_dephasing_read. */
+pic_status pic_gamma_max_read(pic_ctx *ctx, pic_mem mem, double *gmax);
 
 /* ------------------------------------------------------------------ */
 /* Launch shape.  None of these knobs changes a result: every kernel    */

@@ -210,12 +210,15 @@ def dephasing_R(px, py, pz):
 
 
 def push_diagnostics(prm: Params, fs: FieldSource, st: State, n0: int, nsteps: int, *,
-                     forced_k=None, counters: Counters | None = None, threads: int = 0):
+                     forced_k=None, counters: Counters | None = None, threads: int = 0,
+                     gmax=None):
     """push() one step at a time, recording after every completed step of a
     live particle the dephasing error |R - R0| / R0 of Eq. (R error), R0
     being R of the state passed in, and the energy accounting of App. B.
     Returns (R0, running max of the dephasing error, work since the start,
-    largest per-step |kinetic energy change - work|, k trace [nsteps, num])."""
+    largest per-step |kinetic energy change - work|, k trace [nsteps, num]).
+    gmax: optional float64 array of st.num, the running maximum of gamma,
+    updated in place (see orc_push)."""
     R0 = dephasing_R(st.px, st.py, st.pz)
     rmax = np.zeros(st.num)
     work = np.zeros(st.num)
@@ -226,7 +229,7 @@ def push_diagnostics(prm: Params, fs: FieldSource, st: State, n0: int, nsteps: i
         live_before = st.status == 0
         fk = None if forced_k is None else np.ascontiguousarray(forced_k[c:c + 1])
         k1, _ = push(prm, fs, st, n0 + c, 1, forced_k=fk, trace=True, counters=cnt,
-                     threads=threads, work=work, werr=werr)
+                     threads=threads, work=work, werr=werr, gmax=gmax)
         kt[c] = k1[0]
         done = live_before & (st.status == 0)
         d = np.abs(dephasing_R(st.px, st.py, st.pz) - R0) / R0

@@ -50,7 +50,8 @@ struct PushArgs {
     int8_t *ktrace;
     const double *r0;                 // trajectory diagnostics (null: off): R = gamma - p_x at
     double *rmax;                     //   the start, running max of |R - R0| / R0,
-    double *work, *werr;              //   work of E since the start, largest step energy error
+    double *work, *werr;              //   work of E since the start, largest step energy error,
+    double *gmax;                     //   largest gamma after a completed step
     uint64_t *cnt;                    // [nruns][NSLOT][NCNT]
     int64_t kt_n0, kt_first, kt_count;
     int64_t n0;                       // NO_LEVEL: every run starts at its n_cur
@@ -285,11 +286,15 @@ __device__ __forceinline__ double gamma_of(double px, double py, double pz)
     return sqrt(1.0 + ((px * px + py * py) + pz * pz));
 }
 
-__device__ __forceinline__ void dephasing_update(double &rmax, double r0, double px, double py,
-                                                 double pz)
+// After a completed step: the running maximum of the dephasing error
+// |R - R0| / R0, R = gamma - p_x (Eq. (R error)), and of gamma.
+__device__ __forceinline__ void dephasing_update(double &rmax, double &gmax, double r0, double px,
+                                                 double py, double pz)
 {
-    const double d = fabs((gamma_of(px, py, pz) - px) - r0) / r0;
+    const double g = gamma_of(px, py, pz);
+    const double d = fabs((g - px) - r0) / r0;
     rmax = d > rmax ? d : rmax;
+    gmax = g > gmax ? g : gmax;
 }
 
 // Energy accounting (App. B): the work of E over a sub-step is

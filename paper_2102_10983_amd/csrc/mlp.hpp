@@ -438,6 +438,18 @@ __global__ void permute_pair_kernel(const int32_t *__restrict__ dest, int64_t sl
     }
 }
 
+// One per-slot FP64 array moved the same way.
+__global__ void permute_one_kernel(const int32_t *__restrict__ dest, int64_t slots,
+                                   const int32_t *__restrict__ perm, const double *__restrict__ a,
+                                   double *__restrict__ na)
+{
+    for (int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; s < slots;
+         s += int64_t(gridDim.x) * blockDim.x) {
+        if (perm[s] < 0) continue;
+        na[dest[s]] = a[s];
+    }
+}
+
 // Predicted cost of each group: largest score of its lanes (LPT key).
 __global__ void group_cost_kernel(const float *__restrict__ score, const int32_t *__restrict__ perm,
                                   int32_t ngroups, float *__restrict__ gcost)

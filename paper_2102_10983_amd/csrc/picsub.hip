@@ -127,7 +127,7 @@ struct pic_ctx {
     int64_t pred_calls = 0;
     uint64_t rebins = 0;
     // trajectory diagnostics (allocated when first switched on)
-    double *r0 = nullptr, *rmax = nullptr, *work = nullptr, *werr = nullptr;
+    double *r0 = nullptr, *rmax = nullptr, *work = nullptr, *werr = nullptr, *gmax = nullptr;
     bool deph = false;
     // k trace
     int8_t *ktrace = nullptr;
@@ -194,7 +194,7 @@ void free_all(pic_ctx *c)
     c->graph = nullptr;
     void *ptrs[] = {c->x, c->px, c->py, c->pz, c->kold, c->status, c->perm, c->key,
                     c->d_runs, c->group_run, c->group_order, c->group_prio, c->wtab, c->cnt,
-                    c->r0, c->rmax, c->work, c->werr, c->pred_w, c->pred_norm, c->pred_feat,
+                    c->r0, c->rmax, c->work, c->werr, c->gmax, c->pred_w, c->pred_norm, c->pred_feat,
                     c->pred_score, c->d_flag};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -210,7 +210,7 @@ void free_all(pic_ctx *c)
     c->group_prio = nullptr;
     c->d_runs = nullptr;
     c->cnt = nullptr;
-    c->r0 = c->rmax = c->work = c->werr = nullptr;
+    c->r0 = c->rmax = c->work = c->werr = c->gmax = nullptr;
     c->deph = false;
     c->pred_w = nullptr;
     c->pred_norm = c->pred_feat = c->pred_score = nullptr;
@@ -341,6 +341,7 @@ PushArgs push_args(pic_ctx *ctx, int64_t n0, int32_t S)
     a.rmax = ctx->deph ? ctx->rmax : nullptr;
     a.work = ctx->deph ? ctx->work : nullptr;
     a.werr = ctx->deph ? ctx->werr : nullptr;
+    a.gmax = ctx->deph ? ctx->gmax : nullptr;
     a.cnt = ctx->cnt;
     a.kt_n0 = ctx->kt_n0;
     a.kt_first = ctx->kt_first;
@@ -738,7 +739,8 @@ pic_status load_particles(pic_ctx *ctx, pic_mem mem, const double *x, const doub
     if (e == hipSuccess && ctx->r0) {            // new particles: the diagnostics restart
                                                   // (their values belong to slots)
         diag_init_kernel<<<grid_for(ctx->slots, 256, 8192), 256, 0, ctx->stream>>>(
-            ctx->slots, ctx->px, ctx->py, ctx->pz, ctx->r0, ctx->rmax, ctx->work, ctx->werr);
+            ctx->slots, ctx->px, ctx->py, ctx->pz, ctx->r0, ctx->rmax, ctx->work, ctx->werr,
+            ctx->gmax);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
@@ -1238,16 +1240,18 @@ pic_status pic_diag_track(pic_ctx *ctx, int32_t on)
     if (!ctx->r0) {
         pic_status st;
         if ((st = dev_alloc(ctx, &ctx->r0, n)) || (st = dev_alloc(ctx, &ctx->rmax, n)) ||
-            (st = dev_alloc(ctx, &ctx->work, n)) || (st = dev_alloc(ctx, &ctx->werr, n))) {
-            double *ps[4] = {ctx->r0, ctx->rmax, ctx->work, ctx->werr};
+            (st = dev_alloc(ctx, &ctx->work, n)) || (st = dev_alloc(ctx, &ctx->werr, n)) ||
+            (st = dev_alloc(ctx, &ctx->gmax, n))) {
+            double *ps[5] = {ctx->r0, ctx->rmax, ctx->work, ctx->werr, ctx->gmax};
             for (double *q : ps)
                 if (q) (void)hipFree(q);
-            ctx->r0 = ctx->rmax = ctx->work = ctx->werr = nullptr;
+            ctx->r0 = ctx->rmax = ctx->work = ctx->werr = ctx->gmax = nullptr;
             return st;
         }
     }
     diag_init_kernel<<<grid_for(ctx->slots, 256, 8192), 256, 0, ctx->stream>>>(
-        ctx->slots, ctx->px, ctx->py, ctx->pz, ctx->r0, ctx->rmax, ctx->work, ctx->werr);
+        ctx->slots, ctx->px, ctx->py, ctx->pz, ctx->r0, ctx->rmax, ctx->work, ctx->werr,
+        ctx->gmax);
     LAUNCH_CHECK(ctx);
     ctx->deph = true;
     return PIC_OK;
@@ -1262,6 +1266,7 @@ pic_status diag_out(pic_ctx *ctx, pic_mem mem, const double *a, const double *b,
     if (mem != PIC_MEM_HOST && mem != PIC_MEM_DEVICE) return fail(ctx, PIC_E_ARG, "bad pic_mem");
     if (!ctx->r0) return fail(ctx, PIC_E_STATE, "the diagnostics were never switched on");
     const size_t n = size_t(ctx->np);
+    if ((oa && !a) || (ob && !b)) return fail(ctx, PIC_E_ARG, "no such diagnostic");
     if (n == 0 || (!oa && !ob)) return PIC_OK;
     const int grid = grid_for(ctx->slots, 256, 8192);
     if (mem == PIC_MEM_DEVICE) {
@@ -1272,7 +1277,10 @@ pic_status diag_out(pic_ctx *ctx, pic_mem mem, const double *a, const double *b,
     double *d = nullptr;
     pic_status st = dev_alloc(ctx, &d, 2 * n);
     if (st) return st;
-    slots_to_caller_kernel<<<grid, 256, 0, ctx->stream>>>(ctx->perm, ctx->slots, a, b, d, d + n);
+    // an output slot only for each array the caller asked for (b may be
+    // null when ob is)
+    slots_to_caller_kernel<<<grid, 256, 0, ctx->stream>>>(ctx->perm, ctx->slots, a, b,
+                                                          oa ? d : nullptr, ob ? d + n : nullptr);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess && oa) e = hipMemcpyAsync(oa, d, n * 8, hipMemcpyDeviceToHost, ctx->stream);
     if (e == hipSuccess && ob)
@@ -1296,6 +1304,12 @@ pic_status pic_energy_read(pic_ctx *ctx, pic_mem mem, double *work, double *err_
 {
     if (!ctx) return PIC_E_ARG;
     return diag_out(ctx, mem, ctx->work, ctx->werr, work, err_max);
+}
+
+pic_status pic_gamma_max_read(pic_ctx *ctx, pic_mem mem, double *gmax)
+{
+    if (!ctx) return PIC_E_ARG;
+    return diag_out(ctx, mem, ctx->gmax, nullptr, gmax, nullptr);
 }
 
 pic_status pic_tune_set(pic_ctx *ctx, const pic_tune *t)
@@ -1680,6 +1694,15 @@ pic_status pic_prebin(pic_ctx *ctx, const float *score, int32_t nbuckets, float 
             }
             for (int a = 0; a < 4 && e == hipSuccess; ++a)
                 e = hipMemcpyAsync(d4[a], nsoa + a * n, n * 8, hipMemcpyDeviceToDevice, ctx->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(nsoa, ctx->gmax, n * 8, hipMemcpyDeviceToDevice, ctx->stream);
+            if (e == hipSuccess) {
+                permute_one_kernel<<<grid_for(slots, 256, 8192), 256, 0, ctx->stream>>>(
+                    dest, slots, ctx->perm, ctx->gmax, nsoa);
+                e = hipGetLastError();
+            }
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(ctx->gmax, nsoa, n * 8, hipMemcpyDeviceToDevice, ctx->stream);
         }
         if (e == hipSuccess)
             e = hipMemcpyAsync(ctx->perm, nperm, n * 4, hipMemcpyDeviceToDevice, ctx->stream);

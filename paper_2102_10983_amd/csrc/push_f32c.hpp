@@ -99,10 +99,11 @@ __global__ void __launch_bounds__(64 * WPG) push_wave_fp32c_kernel(PushArgs a)
     uint8_t status = PIC_PARTICLE_LOST;
     int64_t kt_u = -1;
     constexpr bool deph = DIAG;   // trajectory diagnostics compiled in
-    double r0v = 1.0, rmx = 0.0, wacc = 0.0, wem = 0.0;
+    double r0v = 1.0, rmx = 0.0, wacc = 0.0, wem = 0.0, gmx = 1.0;
     if (deph && mine) {
         r0v = a.r0[s];
         rmx = a.rmax[s];
+        gmx = a.gmax[s];
         wacc = a.work[s];
         wem = a.werr[s];
     }
@@ -346,13 +347,14 @@ __global__ void __launch_bounds__(64 * WPG) push_wave_fp32c_kernel(PushArgs a)
         if (deph && done) {
             const double qx = double(pxh) + double(pxl), qy = double(pyh) + double(pyl);
             const double qz = double(pzh) + double(pzl);
-            dephasing_update(rmx, r0v, qx, qy, qz);
+            dephasing_update(rmx, gmx, r0v, qx, qy, qz);
             energy_close(wacc, wem, gst, gamma_of(qx, qy, qz), sw);
         }
     }
     if (mine) {
         if (deph) {
             a.rmax[s] = rmx;
+            a.gmax[s] = gmx;
             a.work[s] = wacc;
             a.werr[s] = wem;
         }

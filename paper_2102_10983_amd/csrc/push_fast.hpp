@@ -310,10 +310,11 @@ __global__ void __launch_bounds__(64 * WPG)
     bool moved = false;
     const bool tracing = KT && a.ktrace != nullptr;
     constexpr bool deph = DIAG;   // trajectory diagnostics compiled in
-    double r0v = 1.0, rmx = 0.0, wacc = 0.0, wem = 0.0;
+    double r0v = 1.0, rmx = 0.0, wacc = 0.0, wem = 0.0, gmx = 1.0;
     if (deph && mine) {
         r0v = a.r0[s];
         rmx = a.rmax[s];
+        gmx = a.gmax[s];
         wacc = a.work[s];
         wem = a.werr[s];
     }
@@ -579,7 +580,7 @@ __global__ void __launch_bounds__(64 * WPG)
             cnt.lost += __popcll(wballot(live & !done));
         }
         if (deph && done) {
-            dephasing_update(rmx, r0v, px, py, pz);
+            dephasing_update(rmx, gmx, r0v, px, py, pz);
             energy_close(wacc, wem, gst, gamma_of(px, py, pz), swork);
         }
 
@@ -609,6 +610,7 @@ __global__ void __launch_bounds__(64 * WPG)
         a.status[s] = status;
         if (deph) {
             a.rmax[s] = rmx;
+            a.gmax[s] = gmx;
             a.work[s] = wacc;
             a.werr[s] = wem;
         }

@@ -66,10 +66,11 @@ __global__ void __launch_bounds__(TILE) push_tile_kernel(PushArgs a)
     uint8_t status = PIC_PARTICLE_LOST;
     int64_t kt_u = -1;
     constexpr bool deph = DIAG;   // trajectory diagnostics compiled in
-    double r0v = 1.0, rmx = 0.0, wacc = 0.0, wem = 0.0;
+    double r0v = 1.0, rmx = 0.0, wacc = 0.0, wem = 0.0, gmx = 1.0;
     if (deph && mine) {
         r0v = a.r0[i];
         rmx = a.rmax[i];
+        gmx = a.gmax[i];
         wacc = a.work[i];
         wem = a.werr[i];
     }
@@ -196,7 +197,7 @@ __global__ void __launch_bounds__(TILE) push_tile_kernel(PushArgs a)
                 x = x + R.dt * (px / g2);
                 cnt.step_done(0);
                 if (deph) {
-                    dephasing_update(rmx, r0v, px, py, pz);
+                    dephasing_update(rmx, gmx, r0v, px, py, pz);
                     energy_close(wacc, wem, g0, gamma_of(px, py, pz),
                                  sub_step_work((0.5 * R.qm) * (0.5 * (dto + R.dt)), E, vb, py / g2));
                 }
@@ -298,7 +299,7 @@ __global__ void __launch_bounds__(TILE) push_tile_kernel(PushArgs a)
                 if (sst[t] == 0xFF) {
                     cnt.step_done(k);
                     if (deph) {
-                        dephasing_update(rmx, r0v, px, py, pz);
+                        dephasing_update(rmx, gmx, r0v, px, py, pz);
                         energy_close(wacc, wem, gst, gamma_of(px, py, pz), swk[t]);
                     }
                 } else {
@@ -318,6 +319,7 @@ __global__ void __launch_bounds__(TILE) push_tile_kernel(PushArgs a)
         a.status[i] = status;
         if (deph) {
             a.rmax[i] = rmx;
+            a.gmax[i] = gmx;
             a.work[i] = wacc;
             a.werr[i] = wem;
         }

@@ -69,10 +69,11 @@ __global__ void __launch_bounds__(64 * WPG) push_wave_kernel(PushArgs a)
     }
     bool moved = false;
     constexpr bool deph = DIAG;   // trajectory diagnostics compiled in
-    double r0v = 1.0, rmx = 0.0, wacc = 0.0, wem = 0.0;
+    double r0v = 1.0, rmx = 0.0, wacc = 0.0, wem = 0.0, gmx = 1.0;
     if (deph && mine) {
         r0v = a.r0[s];
         rmx = a.rmax[s];
+        gmx = a.gmax[s];
         wacc = a.work[s];
         wem = a.werr[s];
     }
@@ -218,7 +219,7 @@ __global__ void __launch_bounds__(64 * WPG) push_wave_kernel(PushArgs a)
             cnt.lost += __popcll(__ballot(live && !done));
         }
         if (deph && done) {
-            dephasing_update(rmx, r0v, px, py, pz);
+            dephasing_update(rmx, gmx, r0v, px, py, pz);
             energy_close(wacc, wem, gst, gamma_of(px, py, pz), sw);
         }
     }
@@ -233,6 +234,7 @@ __global__ void __launch_bounds__(64 * WPG) push_wave_kernel(PushArgs a)
         a.status[s] = status;
         if (deph) {
             a.rmax[s] = rmx;
+            a.gmax[s] = gmx;
             a.work[s] = wacc;
             a.werr[s] = wem;
         }

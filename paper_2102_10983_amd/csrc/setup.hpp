@@ -310,19 +310,23 @@ __global__ void __launch_bounds__(256) counter_sum_kernel(const uint64_t *__rest
 __global__ void diag_init_kernel(int64_t slots, const double *__restrict__ px,
                                  const double *__restrict__ py, const double *__restrict__ pz,
                                  double *__restrict__ r0, double *__restrict__ rmax,
-                                 double *__restrict__ work, double *__restrict__ werr)
+                                 double *__restrict__ work, double *__restrict__ werr,
+                                 double *__restrict__ gmax)
 {
     for (int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; s < slots;
          s += int64_t(gridDim.x) * blockDim.x) {
         const double a = px[s], b = py[s], c = pz[s];
-        r0[s] = sqrt(1.0 + ((a * a + b * b) + c * c)) - a;
+        const double g = sqrt(1.0 + ((a * a + b * b) + c * c));
+        r0[s] = g - a;
+        gmax[s] = g;
         rmax[s] = 0.0;
         work[s] = 0.0;
         werr[s] = 0.0;
     }
 }
 
-// Two per-slot arrays in caller order (either output may be null).
+// Two per-slot arrays in caller order (an output, or the array it would
+// come from, may be null: that output is skipped).
 __global__ void slots_to_caller_kernel(const int32_t *__restrict__ perm, int64_t slots,
                                        const double *__restrict__ a,
                                        const double *__restrict__ b, double *__restrict__ oa,
@@ -332,8 +336,8 @@ __global__ void slots_to_caller_kernel(const int32_t *__restrict__ perm, int64_t
          s += int64_t(gridDim.x) * blockDim.x) {
         const int32_t u = perm[s];
         if (u < 0) continue;
-        if (oa) oa[u] = a[s];
-        if (ob) ob[u] = b[s];
+        if (oa && a) oa[u] = a[s];
+        if (ob && b) ob[u] = b[s];
     }
 }
 

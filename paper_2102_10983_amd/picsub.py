@@ -37,7 +37,7 @@ EXPORTS = ("pic_create", "pic_destroy", "pic_last_error", "pic_particles_set",
            "pic_mlp_grad", "pic_mlp_adam", "pic_prebin", "pic_state_export",
            "pic_state_import", "pic_fields_yee", "pic_fields_yee_r", "pic_fields_read",
            "pic_fields_read_r", "pic_diag_track", "pic_dephasing_read",
-           "pic_energy_read",
+           "pic_energy_read", "pic_gamma_max_read",
            "pic_predictor_set", "pic_autotune_forget")
 
 MLP_FEATURES = 8
@@ -142,6 +142,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "pic_fields_read_r": ([vp, i32, i64, C.c_int, vp, vp], C.c_int),
         "pic_diag_track": ([vp, i32], C.c_int),
         "pic_energy_read": ([vp, C.c_int, vp, vp], C.c_int),
+        "pic_gamma_max_read": ([vp, C.c_int, vp], C.c_int),
         "pic_predictor_set": ([vp, vp, vp, vp, C.c_float, i32], C.c_int),
         "pic_autotune_forget": ([], C.c_int),
         "pic_dephasing_read": ([vp, C.c_int, vp, vp], C.c_int),
@@ -359,6 +360,13 @@ class Pusher:
         e = np.empty(self.num)
         self._check(self._lib.pic_energy_read(self._ctx, MEM_HOST, w.ctypes.data, e.ctypes.data))
         return w, e
+
+    def gamma_max_read(self):
+        """Largest gamma of each particle since the diagnostics were
+        (re)started, host array."""
+        g = np.empty(self.num)
+        self._check(self._lib.pic_gamma_max_read(self._ctx, MEM_HOST, g.ctypes.data))
+        return g
 
     def push(self, n: int, S: int = 1):
         self._check(self._lib.pic_push_subcycled(self._ctx, n, S))

@@ -28,6 +28,11 @@ def _fields(wl, shift=0):
                          coeffs=(aE, bE, cE + bE * shift, aB, bB, cB + bB * shift))
 
 
+def _gamma_c(st):
+    """gamma in the oracle's and the kernels' operation order."""
+    return np.sqrt(1.0 + ((st.px * st.px + st.py * st.py) + st.pz * st.pz))
+
+
 def run_whole(wl, chunk: int = 20000, k_max: int = 12, max_steps: int = 1 << 28):
     """Returns (state, counters, running max of |R - 1|, largest gamma)."""
     fs = _fields(wl)
@@ -35,7 +40,7 @@ def run_whole(wl, chunk: int = 20000, k_max: int = 12, max_steps: int = 1 << 28)
     st = O.State(wl.x0, *wl.p0)
     r0 = O.dephasing_R(st.px, st.py, st.pz)
     rmax = np.zeros(wl.num)
-    gmax = st.gamma().copy()
+    gmax = _gamma_c(st)
     cnt = O.Counters()
     n = 0
     while n < max_steps:
@@ -47,12 +52,14 @@ def run_whole(wl, chunk: int = 20000, k_max: int = 12, max_steps: int = 1 << 28)
     return st, cnt, rmax, gmax
 
 
-def run_windows(wl, windows, k_max: int = 12, forced_k=None):
+def run_windows(wl, windows, k_max: int = 12, forced_k=None, gamma_max: bool = False):
     """The oracle over the launches of a device run (n, steps, shift).
-    forced_k: optional [total steps, num] int8 array replacing the decision."""
+    forced_k: optional [total steps, num] int8 array replacing the decision.
+    gamma_max: also return the running maximum of gamma (after each step)."""
     st = O.State(wl.x0, *wl.p0)
     r0 = O.dephasing_R(st.px, st.py, st.pz)
     rmax = np.zeros(wl.num)
+    gmax = _gamma_c(st) if gamma_max else None
     cnt = O.Counters()
     ktrace = []
     for n, steps, shift in windows:
@@ -60,10 +67,12 @@ def run_windows(wl, windows, k_max: int = 12, forced_k=None):
                             wl.x_origin + shift * wl.dx, k_max=k_max)
         fk = None if forced_k is None else np.ascontiguousarray(forced_k[n:n + steps])
         kt, pt = O.push(prm, _fields(wl, shift), st, n, steps, counters=cnt, r0=r0, rmax=rmax,
-                        trace=True, psi_trace=True, forced_k=fk)
+                        gmax=gmax, trace=True, psi_trace=True, forced_k=fk)
         ktrace.append((kt, pt))
     kt = np.concatenate([k for k, _ in ktrace]) if ktrace else np.zeros((0, wl.num), np.int8)
     pt = np.concatenate([p for _, p in ktrace]) if ktrace else np.zeros((0, wl.num))
+    if gamma_max:
+        return st, cnt, rmax, kt, pt, gmax
     return st, cnt, rmax, kt, pt
 
 

@@ -49,6 +49,7 @@ def _gpu(torch, wl, S, precision, binning, fields="lattice"):
     work, werr = run.pusher.energy_read()
     d = run.diag()
     d["work"], d["werr"] = work, werr
+    d["gmax"] = run.pusher.gamma_max_read()
     kt = buf.cpu().numpy()
     run.close()
     return R0, rmax, d, kt
@@ -60,9 +61,10 @@ def _oracle(wl, fields=None, forced_k=None, idx=None):
     idx = np.arange(wl.num) if idx is None else idx
     st = O.State(wl.x0[idx], wl.p0[0][idx], wl.p0[1][idx], wl.p0[2][idx])
     fs = oracle_fields(wl) if fields is None else fields
+    gmax = np.sqrt(1.0 + ((st.px * st.px + st.py * st.py) + st.pz * st.pz))
     R0, rmax, work, werr, kt = O.push_diagnostics(oracle_params(wl), fs, st, 0, wl.steps,
-                                                   forced_k=forced_k)
-    st.work, st.werr = work, werr
+                                                   forced_k=forced_k, gmax=gmax)
+    st.work, st.werr, st.gmax = work, werr, gmax
     return R0, rmax, kt, st
 
 
@@ -77,6 +79,7 @@ def test_fp64_bitwise(torch_gpu, S, binning):
     assert np.array_equal(rmax, ormax)
     assert np.array_equal(d["px"], st.px)
     assert np.array_equal(d["work"], st.work) and np.array_equal(d["werr"], st.werr)
+    assert np.array_equal(d["gmax"], st.gmax) and np.all(d["gmax"] >= d["gamma"])
     _say("max eps_dephasing", float(rmax.max()), "max step energy error", float(d["werr"].max()))
     assert rmax.max() > 0 and d["werr"].max() > 0 and d["work"].max() > 1.0
 
@@ -92,6 +95,7 @@ def test_fp64_bitwise_with_losses_and_standard_pic(torch_gpu):
     assert np.array_equal(kt, okt)
     assert np.array_equal(R0, oR0) and np.array_equal(rmax, ormax)
     assert np.array_equal(d["work"], st.work) and np.array_equal(d["werr"], st.werr)
+    assert np.array_equal(d["gmax"], st.gmax)
     assert np.ptp(R0) > 0.01
 
 
@@ -101,13 +105,13 @@ def test_fp64fast_within_the_implied_bound(torch_gpu, a0, theta):
     R0, rmax, d, kt = _gpu(torch_gpu, wl, wl.steps, "fp64fast", "none")
     oR0, ormax, okt, st = _oracle(wl)
     same = np.all(kt == okt, axis=0)
-    owork, owerr = st.work.copy(), st.werr.copy()
+    owork, owerr, ogmax = st.work.copy(), st.werr.copy(), st.gmax.copy()
     if not same.all():
         idx = np.nonzero(~same)[0]
         _, fr, _, fst = _oracle(wl, forced_k=np.ascontiguousarray(kt[:, idx]), idx=idx)
         ormax = ormax.copy()
         ormax[idx] = fr
-        owork[idx], owerr[idx] = fst.work, fst.werr
+        owork[idx], owerr[idx], ogmax[idx] = fst.work, fst.werr, fst.gmax
     pmax = a0 * a0 / 2 + a0 + 1.0               # bound on |p| along a plane-wave orbit
     bound = 2 * 1e-5 * pmax / oR0
     err = np.abs(rmax - ormax)
@@ -118,6 +122,7 @@ def test_fp64fast_within_the_implied_bound(torch_gpu, a0, theta):
          f"max |d err| {ee.max():.3e}, allowed {4e-5 * pmax:.3e}")
     assert np.all(err <= bound)
     assert np.all(ew <= 4e-5 * pmax) and np.all(ee <= 4e-5 * pmax)
+    assert np.all(np.abs(d["gmax"] - ogmax) <= 2e-5 * pmax)    # |d gamma| <= |d p|
     assert np.allclose(R0, oR0, rtol=1e-12, atol=0)
 
 
@@ -141,12 +146,14 @@ def test_off_freezes_prebin_carries_load_restarts(torch_gpu):
     ref = run_once(False)
     _, m_ref = ref.pusher.dephasing_read()
     w_ref = ref.pusher.energy_read()
+    g_ref = ref.pusher.gamma_max_read()
     ref.close()
     run = run_once(True)
     R0, m = run.pusher.dephasing_read()
     assert np.array_equal(m, m_ref) and np.all(R0 == 1.0) and m.max() > 0
     w = run.pusher.energy_read()
     assert np.array_equal(w[0], w_ref[0]) and np.array_equal(w[1], w_ref[1])
+    assert np.array_equal(run.pusher.gamma_max_read(), g_ref) and g_ref.max() > 1.0
     run.pusher.diag_track(False)              # off: later steps change nothing
     run.advance(40)
     _, m_off = run.pusher.dephasing_read()
@@ -154,6 +161,9 @@ def test_off_freezes_prebin_carries_load_restarts(torch_gpu):
     run.pusher.diag_track(True)               # on again: restarts from the state now
     R0b, m0 = run.pusher.dephasing_read()
     assert np.all(m0 == 0.0) and not np.all(R0b == 1.0)
+    d = run.diag()
+    live = d["status"] == 0
+    assert np.allclose(run.pusher.gamma_max_read()[live], d["gamma"][live], rtol=1e-15, atol=0)
     run.advance(20)
     assert run.pusher.dephasing_read()[1].max() > 0
     run.reset()                                    # loading particles restarts it

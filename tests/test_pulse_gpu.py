@@ -53,7 +53,7 @@ def test_pulse_ieee_is_bit_identical_on_moving_grids(torch_gpu, a0):
     wl = W.pulse_case(a0, 75, 3, 0.01)
     _say(f"pulse IEEE a0={a0}")
     res = _gpu(torch_gpu, wl, "fp64")
-    st, cnt, rmax, _, _ = run_windows(wl, res["windows"])
+    st, cnt, rmax, _, _, gmax = run_windows(wl, res["windows"], gamma_max=True)
     d = res["diag"]
     shifts = [w[2] for w in res["windows"]]
     _say(f"  {res['steps']} steps in {len(shifts)} launches, grid moved {shifts[-1]} cells, "
@@ -61,6 +61,7 @@ def test_pulse_ieee_is_bit_identical_on_moving_grids(torch_gpu, a0):
     for key, ref in (("x", st.x), ("px", st.px), ("py", st.py), ("pz", st.pz)):
         assert np.array_equal(d[key], ref), key
     assert np.array_equal(res["eps_dephasing"], rmax)
+    assert np.array_equal(res["gamma_max"], gmax)
     c = d["counters"]
     assert (c["steps"], c["sub_steps"], c["n_star"]) == (cnt.steps, cnt.sub_steps, cnt.n_star)
     assert shifts[-1] > 10 * wl.ncells and rmax[0] < 0.1
@@ -121,10 +122,13 @@ def test_pulse_claims_on_gpu(torch_gpu):
     """The paper's step-count and energy claims from GPU runs: N* about 20x
     for psi_max 0.01 -> 0.001 (a0 = 50, dt = lambda / 150 c, 1st order;
     Sec. V) and the 1st-order peak gamma about a third of the analytic one at
-    a0 = 100 (Sec. IV; sampled at the launch ends)."""
+    a0 = 100 (Sec. IV; the running maximum after every step).  The bound is
+    the oracle pin's: this 1st-order run amplifies rounding like the others
+    (the oracle's own peak is 0.34 of the analytic one without sub-cycling
+    and 0.26 with it; the fast path's run gives 0.22)."""
     n1 = _gpu(torch_gpu, W.pulse_case(50.0, 150, 1, 0.01), "fp64fast")["diag"]["counters"]["n_star"]
     n2 = _gpu(torch_gpu, W.pulse_case(50.0, 150, 1, 0.001), "fp64fast")["diag"]["counters"]["n_star"]
-    g = _gpu(torch_gpu, W.pulse_case(100.0, 75, 1, 1e30), "fp64fast")["gamma_max_sampled"][0]
+    g = _gpu(torch_gpu, W.pulse_case(100.0, 75, 1, 1e30), "fp64fast")["gamma_max"][0]
     ratio = g / (1.0 + 100.0 ** 2 / 2)
     _say(f"N* {n1} -> {n2} (x{n2 / n1:.1f}); 1st-order peak gamma / analytic {ratio:.3f}")
     assert 14 < n2 / n1 < 28 and 5e4 < n1 < 1e5
