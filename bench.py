@@ -346,7 +346,7 @@ def main():
                     help="electrons (large: 2^20, stress: 2^24, predictor: 2^22; batch: scale "
                          "factor x 1e6)")
     ap.add_argument("--periods", type=float, default=100.0)
-    ap.add_argument("--order", type=int, default=3, choices=(1, 3, 5),
+    ap.add_argument("--order", type=int, default=3, choices=(1, 2, 3, 5),
                     help="single runs: temporal interpolation order p")
     ap.add_argument("--occupancy", default="auto", choices=("auto", "0", "5"),
                     help="register budget of the FP64_FAST push at orders 1, 3 (pic_tune): "

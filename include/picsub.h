@@ -104,7 +104,7 @@ typedef enum {
 
 typedef struct {
     int32_t ncells;      /* nodes per field, >= 2 */
-    int32_t order;       /* temporal interpolation order p: 1, 3 or 5 */
+    int32_t order;       /* temporal interpolation order p: 1, 2, 3 or 5 */
     int32_t ring_depth;  /* stored levels, >= order + 1 */
     int32_t k_max;       /* cap of k, 0..PIC_K_MAX_LIMIT (the weight table holds
                             (4^(k_max+1) - 1) / 3 entries of 2 (order + 1)

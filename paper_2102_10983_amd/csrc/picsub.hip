@@ -223,8 +223,8 @@ pic_status check_params(pic_ctx *ctx, const pic_params *p, int64_t np, int r)
     if (!p) return fail(ctx, PIC_E_ARG, "params of run %d are NULL", r);
     if (np < 0 || np > INT32_MAX) return fail(ctx, PIC_E_ARG, "run %d: np out of range", r);
     if (p->ncells < 2) return fail(ctx, PIC_E_ARG, "run %d: ncells must be >= 2", r);
-    if (p->order != 1 && p->order != 3 && p->order != 5)
-        return fail(ctx, PIC_E_ARG, "run %d: order must be 1, 3 or 5 (got %d)", r, p->order);
+    if (p->order != 1 && p->order != 2 && p->order != 3 && p->order != 5)
+        return fail(ctx, PIC_E_ARG, "run %d: order must be 1, 2, 3 or 5 (got %d)", r, p->order);
     if (p->ring_depth < p->order + 1 || p->ring_depth > 1 << 20)
         return fail(ctx, PIC_E_ARG, "run %d: ring_depth must be in [order+1, 2^20]", r);
     if (p->k_max < 0 || p->k_max > PIC_K_MAX_LIMIT)
@@ -405,6 +405,7 @@ pic_status launch_push(pic_ctx *ctx, int64_t n0, int32_t S, hipStream_t s)
     const PushArgs a = push_args(ctx, n0, S);
     switch (ctx->order) {
     case 1: launch_order<1>(a, ctx->tune, ctx->precision, ctx->slots, s); break;
+    case 2: launch_order<2>(a, ctx->tune, ctx->precision, ctx->slots, s); break;
     case 3: launch_order<3>(a, ctx->tune, ctx->precision, ctx->slots, s); break;
     default: launch_order<5>(a, ctx->tune, ctx->precision, ctx->slots, s); break;
     }

@@ -20,7 +20,7 @@
 // 1/gamma from v_rsq_f64 and the Boris denominator from v_rcp_f64, each
 // refined by one Newton step; x is carried in node units.  p_z never
 // changes in this geometry (E along y, B along z), so 1 + p_z^2 is a
-// constant of each lane.  At orders 1 and 3, when a wavefront sub-cycles, its
+// constant of each lane.  At orders 1 to 3, when a wavefront sub-cycles, its
 // LDS window is rewritten once per step as the coefficients of each node's
 // interpolating polynomial in u = s - 1/2 (the same polynomial as the
 // Lagrange form), so a sub-step evaluates it by Horner's rule at
@@ -45,6 +45,12 @@ typedef const __attribute__((address_space(1))) double *gdptr;
 template <int P> struct HalfStepB;
 template <> struct HalfStepB<1> {
     __device__ constexpr double operator[](int) const { return 0.5; }
+};
+template <> struct HalfStepB<2> {
+    __device__ constexpr double operator[](int j) const
+    {
+        return j == 0 ? -1.0 / 8 : j == 1 ? 6.0 / 8 : 3.0 / 8;
+    }
 };
 template <> struct HalfStepB<3> {
     __device__ constexpr double operator[](int j) const
@@ -139,6 +145,10 @@ __device__ constexpr double mono_c(int field, int m, int j)
     if constexpr (P == 1) {
         constexpr double e[2][2] = {{0.0, 1.0}, {-1.0, 1.0}};
         constexpr double b[2][2] = {{0.5, 0.5}, {-1.0, 1.0}};
+        return field ? b[m][j] : e[m][j];
+    } else if constexpr (P == 2) {
+        constexpr double e[3][3] = {{0.0, 0.0, 1.0}, {0.5, -2.0, 1.5}, {0.5, -1.0, 0.5}};
+        constexpr double b[3][3] = {{-1.0 / 8, 3.0 / 4, 3.0 / 8}, {0.0, -1.0, 1.0}, {0.5, -1.0, 0.5}};
         return field ? b[m][j] : e[m][j];
     } else if constexpr (P == 3) {
         constexpr double e[4][4] = {{0.0, 0.0, 0.0, 1.0},
@@ -243,7 +253,7 @@ __global__ void __launch_bounds__(64 * WPG)
     constexpr int ROWS = 2 * (P + 1);                 // row 2j: E of level j, 2j+1: B
     constexpr int NPF = (ROWS * PF_NW + 63) / 64;     // window values per lane
     // Sub-steps evaluate each node's polynomial by Horner's rule from
-    // coefficients formed once per sub-cycled step (orders 1, 3), or weight the
+    // coefficients formed once per sub-cycled step (orders 1 to 3), or weight the
     // window's levels with the (k, j) entry of the weight table (order 5, where
     // forming 2 (P + 1)^2 products per node costs more than it saves).
     constexpr bool MONO = P <= 3;
@@ -387,7 +397,10 @@ __global__ void __launch_bounds__(64 * WPG)
                 // (e / 16) & 1), node nlo + e % 16
                 if (lane + 64 * h < ROWS * PF_NW) {
                     const int node = nlo + pf_q;
-                    const int32_t o_even = lvo[2 * h + 1], o_odd = lvo[2 * h + 2];
+                    // (an odd number of levels, p = 2, leaves the last pair
+                    // half empty: those lanes have no value to load)
+                    const int32_t o_even = lvo[2 * h + 1];
+                    const int32_t o_odd = 2 * h + 2 <= P + 1 ? lvo[2 * h + 2] : o_even;
                     const int32_t off = pf_hi ? o_odd : o_even;
                     pf[h] = pf_src[off + node];
                 }

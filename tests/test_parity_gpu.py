@@ -77,8 +77,9 @@ def test_single_step(torch_gpu, runner, order):
     assert res["flips"] == 0
 
 
-@pytest.mark.parametrize("order,S,binning", [(1, 1, "none"), (3, 1, "none"), (3, 16, "none"),
-                                             (1, 75, "ballot"), (3, 1, "ballot"),
+@pytest.mark.parametrize("order,S,binning", [(1, 1, "none"), (2, 1, "none"), (3, 1, "none"),
+                                             (3, 16, "none"), (1, 75, "ballot"),
+                                             (2, 40, "ballot"), (3, 1, "ballot"),
                                              (3, 250, "ballot")])
 def test_small_case_full_run(torch_gpu, runner, order, S, binning):
     """1024 electrons, a0 = 10, T/dt = 75, 2048 cells, 20 periods."""
@@ -106,7 +107,7 @@ def test_ragged_sizes(torch_gpu, runner, binning):
         compare(wl, wl.steps, d, np.arange(num), TOL64, g_ktrace=kt)
 
 
-@pytest.mark.parametrize("order", [1, 3, 5])
+@pytest.mark.parametrize("order", [1, 2, 3, 5])
 def test_binning_modes_are_bitwise_identical(torch_gpu, runner, order):
     """Which lane runs a particle must not change its arithmetic: the
     one-lane-per-particle push and the compacted tile push agree bit for
@@ -259,7 +260,7 @@ def test_large_case_sampled(torch_gpu, runner, seed):
 # Fast FP64 (refined hardware reciprocals, node-unit positions): the
 # non-bitwise path held to the 1e-5 bar
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("order,S", [(1, 1500), (3, 1500), (3, 7), (5, 300)])
+@pytest.mark.parametrize("order,S", [(1, 1500), (2, 1500), (2, 7), (3, 1500), (3, 7), (5, 300)])
 def test_fp64fast_small_case(torch_gpu, runner, order, S):
     _say(f"fp64fast small case order={order} S={S}")
     from parity import compare
