@@ -202,7 +202,7 @@ def test_lost_wavefronts_fp64fast(torch_gpu, runner, S):
 def test_error_codes(torch_gpu):
     from paper_2102_10983_amd import picsub
     with pytest.raises(picsub.PicError) as e:
-        picsub.Pusher(num=4, ncells=16, order=2, dx=1.0, dt=0.5, psi_max=0.01)
+        picsub.Pusher(num=4, ncells=16, order=4, dx=1.0, dt=0.5, psi_max=0.01)
     assert e.value.status == 1
     with pytest.raises(picsub.PicError) as e:
         picsub.Pusher(num=4, ncells=16, order=3, dx=1.0, dt=0.5, psi_max=0.01, ring_depth=3)
