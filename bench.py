@@ -89,10 +89,10 @@ def source_hash(files) -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(key: str, launches_per_step: int, workload: str):
-    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE runs, if they were taken on this workload with the kernel as
-    built now."""
+def measured_record(key: str, launches_per_step: int, workload: str, field: str):
+    """A per-launch figure from the committed rocprofv3 runs (HBM bytes from
+    FETCH_SIZE / WRITE_SIZE, VALU instructions from SQ_INSTS_VALU), if they
+    were taken on this workload with the kernel as built now."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     with open(TRAFFIC_FILE) as fh:
@@ -100,7 +100,14 @@ def measured_traffic(key: str, launches_per_step: int, workload: str):
     name, files = KERNELS[key]
     if not rec or rec.get("source_hash") != source_hash(files):
         return None
-    return rec["bytes_per_launch"] if launches_per_step == rec.get("launches_per_pass", 1) else None
+    if launches_per_step != rec.get("launches_per_pass", 1):
+        return None
+    return rec.get(field)
+
+
+def measured_traffic(key: str, launches_per_step: int, workload: str):
+    """HBM bytes per launch (see measured_record)."""
+    return measured_record(key, launches_per_step, workload, "bytes_per_launch")
 
 
 def cpu_model() -> str:
@@ -521,6 +528,18 @@ def main():
             p.close()
             compare.append(leg)
 
+    # the attainable FP64 vector rate on this device (FMA chains, 16 per lane,
+    # 32 waves per CU), best of three launches after one to warm up
+    from paper_2102_10983_amd import picsub as PS
+    PS.fma_probe(2048, 1000)
+    attainable = max(PS.fma_probe(2048, 100000) for _ in range(3))
+    # VALU issue bound: the push launch's wave-level VALU instructions (from
+    # the committed rocprofv3 SQ_INSTS_VALU count of this kernel on this
+    # workload), 4 cycles each on one of 1024 SIMDs at 2.4 GHz
+    valu = (measured_record(key, launches_per_step, args.workload, "valu_instr_per_launch")
+            if traffic is not None else None)
+    ieee = [c for c in compare if c["precision"] == "fp64" and c["binning"] == "none"
+            and c["workload"] == args.workload]
     res = {
         "metric": "sub-step particle pushes/sec at rel err<=1e-5 vs FP64 oracle; "
                   "learned-binned vs plain",
@@ -554,7 +573,14 @@ def main():
                                    f"{FLOPS_PER_DECISION} per step of dt",
                      "model_flops_per_launch": model_step * args.steps / launches,
                      "model_frac": model_step * args.steps / (kernel_ms / 1e3) / 1e12
-                                   / PEAK_FP64_TFLOPS},
+                                   / PEAK_FP64_TFLOPS,
+                     "attainable_peak": attainable,
+                     "frac_attainable": achieved / attainable,
+                     "attainable_from": "FMA-chain probe: 2048 x 256 lanes, 16 chains of 1e5 "
+                                        "FMAs each, best of 3",
+                     "valu_issue_frac": (valu * 4 / (1024 * 2.4e9)) / (kernel_ms / launches / 1e3)
+                                        if valu else None},
+        "speedup_vs_plain_fp64": (value / ieee[0]["value"]) if ieee else None,
     }
     if do_cpu:
         threads = len(os.sched_getaffinity(0))

@@ -379,6 +379,14 @@ pic_status pic_dephasing_read(pic_ctx *ctx, pic_mem mem, double *R0,
 pic_status pic_energy_read(pic_ctx *ctx, pic_mem mem, double *work,
                            double *err_max);
 
+/* Measurement aid, not part of the method: the attainable FP64 vector FMA
+ * rate.  Launches `blocks` workgroups of 256 lanes on hip_stream; each lane
+ * runs 16 independent FMA chains of `iters` rounds (2 * 16 * iters flop per
+ * lane) and writes one double to out (device, blocks * 256 doubles, owned
+ * by the caller).  Asynchronous; PIC_E_ARG for a null out or non-positive
+ * sizes. */
+pic_status pic_fma_probe(double *out, int32_t blocks, int64_t iters, void *hip_stream);
+
 /* The largest gamma of every particle since the diagnostics were (re)started
  * (np doubles, caller order), as pic_dephasing_read. */
 pic_status pic_gamma_max_read(pic_ctx *ctx, pic_mem mem, double *gmax);

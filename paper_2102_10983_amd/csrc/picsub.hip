@@ -1307,6 +1307,14 @@ pic_status pic_energy_read(pic_ctx *ctx, pic_mem mem, double *work, double *err_
     return diag_out(ctx, mem, ctx->work, ctx->werr, work, err_max);
 }
 
+pic_status pic_fma_probe(double *out, int32_t blocks, int64_t iters, void *hip_stream)
+{
+    if (!out || blocks < 1 || iters < 1) return PIC_E_ARG;
+    fma_probe_kernel<<<blocks, 256, 0, (hipStream_t)hip_stream>>>(out, iters, 1.0 - 0x1p-30,
+                                                                  0x1p-30);
+    return hipGetLastError() == hipSuccess ? PIC_OK : PIC_E_DEVICE;
+}
+
 pic_status pic_gamma_max_read(pic_ctx *ctx, pic_mem mem, double *gmax)
 {
     if (!ctx) return PIC_E_ARG;

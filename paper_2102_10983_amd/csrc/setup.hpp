@@ -341,4 +341,24 @@ __global__ void slots_to_caller_kernel(const int32_t *__restrict__ perm, int64_t
     }
 }
 
+// Attainable FP64 vector rate on this device (a measurement aid, not part of
+// the method): every lane runs 16 independent chains of fused multiply-adds,
+// enough to cover the FMA latency, `iters` rounds each; the sums are stored
+// so that none of the work can be dropped.
+__global__ void __launch_bounds__(256) fma_probe_kernel(double *__restrict__ out, int64_t iters,
+                                                        double a, double b)
+{
+    double v[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = double(threadIdx.x + i);
+    for (int64_t it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) v[i] = fma(v[i], a, b);
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) s += v[i];
+    out[int64_t(blockIdx.x) * blockDim.x + threadIdx.x] = s;
+}
+
 }  // namespace picsub

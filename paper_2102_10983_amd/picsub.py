@@ -37,7 +37,7 @@ EXPORTS = ("pic_create", "pic_destroy", "pic_last_error", "pic_particles_set",
            "pic_mlp_grad", "pic_mlp_adam", "pic_prebin", "pic_state_export",
            "pic_state_import", "pic_fields_yee", "pic_fields_yee_r", "pic_fields_read",
            "pic_fields_read_r", "pic_diag_track", "pic_dephasing_read",
-           "pic_energy_read", "pic_gamma_max_read",
+           "pic_energy_read", "pic_gamma_max_read", "pic_fma_probe",
            "pic_predictor_set", "pic_autotune_forget")
 
 MLP_FEATURES = 8
@@ -143,6 +143,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "pic_diag_track": ([vp, i32], C.c_int),
         "pic_energy_read": ([vp, C.c_int, vp, vp], C.c_int),
         "pic_gamma_max_read": ([vp, C.c_int, vp], C.c_int),
+        "pic_fma_probe": ([vp, i32, C.c_int64, vp], C.c_int),
         "pic_predictor_set": ([vp, vp, vp, vp, C.c_float, i32], C.c_int),
         "pic_autotune_forget": ([], C.c_int),
         "pic_dephasing_read": ([vp, C.c_int, vp, vp], C.c_int),
@@ -578,6 +579,23 @@ def _stream_ptr():
 def _mlp_status(st: int, what: str):
     if st != 0:
         raise PicError(st, what)
+
+
+def fma_probe(blocks: int, iters: int):
+    """Attainable FP64 vector rate: times one launch of the FMA-chain probe on
+    torch's current stream; returns TFLOP/s."""
+    torch = _torch()
+    L = load_library()
+    out = torch.empty(int(blocks) * 256, dtype=torch.float64, device="cuda")
+    s = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    _mlp_status(L.pic_fma_probe(_dev_ptr(out, torch.float64), int(blocks), int(iters),
+                                _stream_ptr()), "fma probe")
+    e1.record(s)
+    e1.synchronize()
+    return 2.0 * 16 * iters * blocks * 256 / (e0.elapsed_time(e1) * 1e-3) / 1e12
 
 
 def mlp_forward(w_bf16, norm, feat, out=None):

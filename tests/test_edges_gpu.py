@@ -170,3 +170,16 @@ def test_diag_of_one_run(torch_gpu):
         assert dr["counters"]["steps"] > 0
         off += wl.num
     br.close()
+
+
+def test_fma_probe(torch_gpu):
+    """The attainable-rate probe: a small launch gives a positive rate below
+    the vendor's FP64 vector peak (78.6 TFLOP/s at 2.4 GHz), and it refuses
+    empty launches."""
+    from paper_2102_10983_amd import picsub
+    rate = picsub.fma_probe(64, 2000)
+    assert 0 < rate < 80.0
+    out = torch_gpu.empty(256, dtype=torch_gpu.float64, device="cuda")
+    L = picsub.load_library()
+    assert L.pic_fma_probe(out.data_ptr(), 1, 0, None) == 1
+    assert L.pic_fma_probe(None, 1, 10, None) == 1
