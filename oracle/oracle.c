@@ -258,13 +258,14 @@ int orc_push(const orc_params *prm, const orc_fields *f, int64_t np,
              int8_t *k_old, uint8_t *status, int64_t n0, int32_t nsteps,
              const int8_t *forced_k, int8_t *k_trace, double *psi_trace,
              double *work, double *werr, const double *r0, double *rmax, double *gmax,
-             orc_counters *cnt, int32_t nthreads)
+             const double *ai, double *emax, orc_counters *cnt, int32_t nthreads)
 {
     if (!prm || !f || np < 0 || nsteps < 0) return -1;
     if (prm->order < 1 || prm->order > ORC_MAX_ORDER) return -1;
     if (prm->ncells < 2 || !(prm->dx > 0) || !(prm->dt > 0)) return -1;
     if (prm->k_max < 0 || prm->k_max > 12) return -1;
     if (f->mode == 1 && f->M <= 0) return -1;
+    if (emax && (!ai || f->mode != 1 || !f->atab)) return -1;
     if (!levels_present(prm, f, n0, nsteps)) return -2;
 
     local_cnt total;
@@ -315,6 +316,26 @@ int orc_push(const orc_params *prm, const orc_fields *f, int64_t np,
                         if (dr > rmax[i]) rmax[i] = dr;
                     }
                     if (gmax && g_end > gmax[i]) gmax[i] = g_end;
+                }
+                if (rc == 0 && emax) {
+                    /* energy error against gamma_th = 1 + (a - a_i)^2 / 2 at
+                     * the phase of the momentum, which lags x by half of the
+                     * step's last sub-step */
+                    double g_end = sqrt(1.0 + ((px[i] * px[i] + py[i] * py[i]) + pz[i] * pz[i]));
+                    double half = 0.5 * ldexp(1.0, -2 * k);          /* dt* / 2, in dt */
+                    double tau = (double)(n0 + st + 1) - half;
+                    double xp = x[i] - half * prm->dt * (px[i] / g_end);
+                    double u = (xp - prm->x_origin) / prm->dx - 0.5;  /* E-node coordinate */
+                    double m = (double)f->aE * tau + (double)f->bE * u + (double)f->cE;
+                    double mf = floor(m);
+                    int64_t j0 = (int64_t)mf % f->M;
+                    if (j0 < 0) j0 += f->M;
+                    int64_t j1 = j0 + 1 == f->M ? 0 : j0 + 1;
+                    double a = f->atab[j0] + (m - mf) * (f->atab[j1] - f->atab[j0]);
+                    double d = a - ai[i];
+                    double g_th = 1.0 + 0.5 * (d * d);
+                    double e = fabs(g_end - g_th) / g_th;
+                    if (e > emax[i]) emax[i] = e;
                 }
                 if (rc == 1) {
                     status[i] = ORC_LOST;

@@ -65,7 +65,9 @@ typedef struct {
 
 /* Field source.  Level m: E at t = m dt, B at t = (m + 1/2) dt.
  * mode 0: explicit arrays E[(m - lev0) * ncells + i], same for B;
- * mode 1: lattice table, F = table[((a m + b i + c) mod M)]. */
+ * mode 1: lattice table, F = table[((a m + b i + c) mod M)].
+ * atab (mode 1, may be NULL): the wave's vector potential a on the same
+ * lattice (atab[j] at the phase of table[j]), for the energy error. */
 typedef struct {
     int32_t mode;
     int32_t nlev;
@@ -74,6 +76,7 @@ typedef struct {
     const double *table;
     int64_t M;
     int64_t aE, bE, cE, aB, bB, cB;
+    const double *atab;
 } orc_fields;
 
 /* Steps are counted when all their sub-steps are done (a particle lost
@@ -121,6 +124,13 @@ void orc_boris(double qm, double dtp, double E, double B,
  * keeps the largest |R - r0[i]| / r0[i], R = gamma - p_x of the momentum
  * (the dephasing error of Sec. IV, Eq. (R error)); gmax (may be NULL) keeps
  * the largest gamma.
+ * ai, emax (np each, may be NULL; need f->atab): after every completed
+ * step emax[i] keeps the largest |gamma - gamma_th| / gamma_th (the energy
+ * error of Sec. IV, Eq. (gamma error)), gamma_th = 1 + (a - ai[i])^2 / 2
+ * (Eq. (theoretical gamma) for an electron that started at rest where
+ * a = ai[i]) with a taken at the phase of the momentum: t_p = (n + 1) dt -
+ * dt* / 2 and x(t_p) = x - v_x dt* / 2 (dt* of the step just completed), a
+ * linear between lattice points.
  * k_old[i] < 0 means "no previous sub-step": the first transition push
  * then uses dt*_new.  forced_k ([nsteps][np], may be NULL) replaces the
  * decision; k_trace and psi_trace ([nsteps][np], may be NULL) record the
@@ -132,7 +142,7 @@ int orc_push(const orc_params *prm, const orc_fields *f, int64_t np,
              int8_t *k_old, uint8_t *status, int64_t n0, int32_t nsteps,
              const int8_t *forced_k, int8_t *k_trace, double *psi_trace,
              double *work, double *werr, const double *r0, double *rmax, double *gmax,
-             orc_counters *cnt, int32_t nthreads);
+             const double *ai, double *emax, orc_counters *cnt, int32_t nthreads);
 
 /* number of OpenMP threads the library would use */
 int32_t orc_max_threads(void);

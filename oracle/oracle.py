@@ -38,7 +38,8 @@ class Fields(C.Structure):
     _fields_ = [("mode", C.c_int32), ("nlev", C.c_int32), ("lev0", C.c_int64),
                 ("E", C.c_void_p), ("B", C.c_void_p), ("table", C.c_void_p),
                 ("M", C.c_int64), ("aE", C.c_int64), ("bE", C.c_int64), ("cE", C.c_int64),
-                ("aB", C.c_int64), ("bB", C.c_int64), ("cB", C.c_int64)]
+                ("aB", C.c_int64), ("bB", C.c_int64), ("cB", C.c_int64),
+                ("atab", C.c_void_p)]
 
 
 class Counters(C.Structure):
@@ -77,7 +78,7 @@ def lib():
                                C.c_void_p, C.c_void_p, C.c_int64, C.c_int32,
                                C.c_void_p, C.c_void_p, C.c_void_p,
                                C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
-                               C.POINTER(Counters), C.c_int32]
+                               C.c_void_p, C.c_void_p, C.POINTER(Counters), C.c_int32]
         L.orc_push.restype = C.c_int
         L.orc_max_threads.restype = C.c_int32
         _lib = L
@@ -112,12 +113,17 @@ class FieldSource:
     """Explicit levels (E[L, ncells], B[L, ncells] from level lev0) or a
     lattice table (F = table[(a n + b i + c) mod M])."""
 
-    def __init__(self, *, E=None, B=None, lev0=0, table=None, M=0, coeffs=None):
+    def __init__(self, *, E=None, B=None, lev0=0, table=None, M=0, coeffs=None, atab=None):
         self.s = Fields()
         if table is not None:
             self._keep = (np.ascontiguousarray(table, dtype=np.float64),)
             self.s.mode = 1
             self.s.table = self._keep[0].ctypes.data
+            if atab is not None:
+                at = np.ascontiguousarray(atab, dtype=np.float64)
+                assert at.shape == self._keep[0].shape
+                self._keep = self._keep + (at,)
+                self.s.atab = at.ctypes.data
             self.s.M = int(M)
             (self.s.aE, self.s.bE, self.s.cE, self.s.aB, self.s.bB, self.s.cB) = (
                 int(c) for c in coeffs)
@@ -175,15 +181,19 @@ class State:
 
 def push(prm: Params, fs: FieldSource, st: State, n0: int, nsteps: int, *,
          forced_k=None, trace=False, psi_trace=False, counters: Counters | None = None,
-         threads: int = 0, work=None, werr=None, r0=None, rmax=None, gmax=None):
+         threads: int = 0, work=None, werr=None, r0=None, rmax=None, gmax=None,
+         ai=None, emax=None):
     """Advance the state in place; returns (k_trace, psi_trace) arrays or None.
     work, werr: float64 arrays of st.num updated in place (App. B energy
     accounting); r0, rmax: the dephasing error of Eq. (R error) against r0,
-    running maximum kept in rmax; gmax: running maximum of gamma (see
-    orc_push)."""
+    running maximum kept in rmax; gmax: running maximum of gamma; ai, emax:
+    the energy error of Eq. (gamma error), running maximum kept in emax
+    (needs a field source with atab; see orc_push)."""
     if r0 is not None:
         r0 = np.ascontiguousarray(r0, dtype=np.float64)
-    for a in (work, werr, rmax, gmax):
+    if ai is not None:
+        ai = np.ascontiguousarray(ai, dtype=np.float64)
+    for a in (work, werr, rmax, gmax, emax):
         if a is not None:
             assert a.dtype == np.float64 and a.shape == (st.num,) and a.flags.c_contiguous
     kt = np.empty((nsteps, st.num), dtype=np.int8) if trace else None
@@ -195,7 +205,8 @@ def push(prm: Params, fs: FieldSource, st: State, n0: int, nsteps: int, *,
     rc = lib().orc_push(C.byref(prm), C.byref(fs.s), st.num, _ptr(st.x), _ptr(st.px),
                         _ptr(st.py), _ptr(st.pz), _ptr(st.k_old), _ptr(st.status),
                         n0, nsteps, _ptr(fk), _ptr(kt), _ptr(pt), _ptr(work), _ptr(werr),
-                        _ptr(r0), _ptr(rmax), _ptr(gmax), C.byref(cnt), threads)
+                        _ptr(r0), _ptr(rmax), _ptr(gmax), _ptr(ai), _ptr(emax),
+                        C.byref(cnt), threads)
     if rc != 0:
         raise ValueError(f"orc_push failed ({rc})")
     return kt, pt

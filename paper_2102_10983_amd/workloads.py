@@ -118,6 +118,27 @@ def plane_wave_table(lat: Lattice, a0: float, kind: str = "flat",
     raise ValueError(f"unknown wave kind {kind!r}")
 
 
+def potential_table(lat: Lattice, a0: float, kind: str = "flat",
+                    xi0: float = GAUSS_XI0, sigma: float = GAUSS_SIGMA,
+                    m_lo: int | None = None, m_count: int | None = None):
+    """The vector potential a itself on the lattice of plane_wave_table, with
+    the same (table, M, shift) layout (for the energy error of the model
+    problem, whose analytic gamma is 1 + (a - a_i)^2 / 2)."""
+    if kind == "flat":
+        m = np.arange(lat.period, dtype=np.int64)
+        xi = m.astype(np.float64) * lat.unit
+        return a0 * np.sin(xi), lat.period, 0
+    if kind == "gauss":
+        if m_lo is None:
+            m_lo = -int(math.ceil(GAUSS_MARGIN / lat.unit))
+        if m_count is None:
+            m_count = int(math.ceil((xi0 + 9.0 * sigma + GAUSS_MARGIN) / lat.unit)) - m_lo + 1
+        m = np.arange(m_lo, m_lo + m_count, dtype=np.int64)
+        xi = m.astype(np.float64) * lat.unit
+        return a0 * np.exp(-((xi - xi0) ** 2) / (2.0 * sigma * sigma)) * np.sin(xi), m_count, m_lo
+    raise ValueError(f"unknown wave kind {kind!r}")
+
+
 def shifted_coeffs(lat: Lattice, shift: int):
     """Lattice coefficients with a table shift folded into c."""
     aE, bE, cE, aB, bB, cB = lat.coeffs()
@@ -185,6 +206,9 @@ class Workload:
 
     def table(self):
         return plane_wave_table(self.lat, self.a0, self.kind)
+
+    def potential(self):
+        return potential_table(self.lat, self.a0, self.kind)
 
 
 def make_workload(name: str, num: int, a0: float, n_t: int, ncells: int,

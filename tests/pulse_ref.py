@@ -33,9 +33,33 @@ def _gamma_c(st):
     return np.sqrt(1.0 + ((st.px * st.px + st.py * st.py) + st.pz * st.pz))
 
 
-def run_whole(wl, chunk: int = 20000, k_max: int = 12, max_steps: int = 1 << 28):
-    """Returns (state, counters, running max of |R - 1|, largest gamma)."""
-    fs = _fields(wl)
+def a_on_lattice(wl, atab, M, coeffs, tau, x):
+    """a at time tau dt and position x on the E lattice, linear between
+    lattice points (the oracle's own rule for the energy error)."""
+    aE, bE, cE = coeffs[0], coeffs[1], coeffs[2]
+    m = aE * tau + bE * ((np.asarray(x) - wl.x_origin) / wl.dx - 0.5) + cE
+    mf = np.floor(m)
+    j0 = mf.astype(np.int64) % M
+    j1 = (j0 + 1) % M
+    return atab[j0] + (m - mf) * (atab[j1] - atab[j0])
+
+
+def run_whole(wl, chunk: int = 20000, k_max: int = 12, max_steps: int = 1 << 28,
+              energy: bool = False):
+    """Returns (state, counters, running max of |R - 1|, largest gamma), and
+    with energy=True also the running maximum of the energy error of
+    Eq. (gamma error) (a_i: a at the electron's phase when its momentum is
+    zero, half a step before the start)."""
+    if energy:
+        table, M, tshift = wl.table()
+        atab, _, _ = wl.potential()
+        co = W.shifted_coeffs(wl.lat, tshift)
+        fs = O.FieldSource(table=table, M=M, coeffs=co, atab=atab)
+        ai = a_on_lattice(wl, atab, M, co, -0.5, wl.x0)
+        emax = np.zeros(wl.num)
+    else:
+        fs = _fields(wl)
+        ai = emax = None
     prm = O.make_params(2_000_000, wl.order, wl.dx, wl.dt, wl.psi_max, wl.x_origin, k_max=k_max)
     st = O.State(wl.x0, *wl.p0)
     r0 = O.dephasing_R(st.px, st.py, st.pz)
@@ -44,11 +68,13 @@ def run_whole(wl, chunk: int = 20000, k_max: int = 12, max_steps: int = 1 << 28)
     cnt = O.Counters()
     n = 0
     while n < max_steps:
-        O.push(prm, fs, st, n, chunk, counters=cnt, r0=r0, rmax=rmax, gmax=gmax)
+        O.push(prm, fs, st, n, chunk, counters=cnt, r0=r0, rmax=rmax, gmax=gmax, ai=ai, emax=emax)
         n += chunk
         live = st.status == 0
         if not live.any() or np.all(n * wl.dt - st.x[live] > XI_END):
             break
+    if energy:
+        return st, cnt, rmax, gmax, emax
     return st, cnt, rmax, gmax
 
 

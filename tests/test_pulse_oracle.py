@@ -136,3 +136,49 @@ def test_fifth_order_keeps_the_step_count_and_the_accuracy(a0):
         d[order] = (r[0], c.n_star / (c.n_star + c.steps))
     assert abs(d[5][1] - d[3][1]) < 0.15 * d[3][1]
     assert d[5][0] < 0.1 and d[1][0] > 10 * d[5][0]
+
+
+def _energy_error_flat(n_t):
+    """Largest energy error of 64 electrons at rest in a flat a0 = 1 wave over
+    two periods, 1st order, no sub-cycling."""
+    from oracle import oracle as O
+    from pulse_ref import a_on_lattice
+    wl = W.make_workload("e", 64, 1.0, n_t, 4 * n_t, 2.0, 1, 1e30, 1.0, seed=5)
+    table, M, shift = wl.table()
+    atab, _, _ = wl.potential()
+    co = W.shifted_coeffs(wl.lat, shift)
+    fs = O.FieldSource(table=table, M=M, coeffs=co, atab=atab)
+    prm = O.make_params(wl.ncells, 1, wl.dx, wl.dt, wl.psi_max, wl.x_origin)
+    st = O.State(wl.x0, *wl.p0)
+    emax = np.zeros(wl.num)
+    O.push(prm, fs, st, 0, wl.steps, ai=a_on_lattice(wl, atab, M, co, -0.5, wl.x0), emax=emax)
+    return float(emax.max())
+
+
+def test_energy_error_converges_at_second_order():
+    """The energy error of Eq. (gamma error) against Eq. (theoretical gamma)
+    on a flat wave falls 4x per halving of dt: the integrator is second order
+    and gamma_th is taken at the phase of the momentum (half a sub-step
+    behind x).  Taking it at the phase of x instead leaves an O(dt) error
+    (first order, 30x larger at T/dt = 150), which this fails."""
+    e = [_energy_error_flat(n) for n in (150, 300, 600)]
+    assert e[0] < 1e-3
+    for a, b in zip(e, e[1:]):
+        assert 3.5 < a / b < 4.6, e
+
+
+def test_first_order_energy_error_grows_with_a0():
+    """Sec. IV (Fig. 2b): with 1st-order interpolation and no sub-cycling at
+    dt = lambda / 75 c, epsilon_energy increases almost monotonically with
+    a0 and becomes significant beyond a0 ~ 40; 3rd order with sub-cycling
+    keeps it an order of magnitude lower there (measured: 0.02, 0.07, 0.40,
+    1.7, 9.8 against 0.003, 0.005, 0.05, 0.06, 0.19 for a0 = 5, 10, 25, 50,
+    100)."""
+    e1, e3 = [], []
+    for a0 in (5.0, 10.0, 25.0, 50.0, 100.0):
+        e1.append(float(run_whole(W.pulse_case(a0, 75, 1, 1e30), chunk=1000, energy=True)[4][0]))
+        e3.append(float(run_whole(W.pulse_case(a0, 75, 3, 0.01), chunk=1000, energy=True)[4][0]))
+    assert all(a < b for a, b in zip(e1, e1[1:])), e1
+    assert e1[0] < 0.05 and min(e1[3:]) > 1.0, e1
+    assert e3[2] < 0.2 * e1[2], (e1, e3)
+    assert all(b < 0.1 * a for a, b in zip(e1[3:], e3[3:])), (e1, e3)
