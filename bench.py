@@ -475,7 +475,9 @@ def main():
                 ("plain FP64 push (IEEE div/sqrt)", args.workload, "fp64", "none", args.fields,
                  args.steps),
                 ("FP32-compensated push, same binning", args.workload, "fp32c", args.binning,
-                 args.fields, args.steps)]
+                 args.fields, args.steps),
+                ("compaction by k alone: the ballot kernel (per-step ballot + per-k LDS "
+                 "queues, IEEE FP64)", args.workload, "fp64", "ballot", args.fields, 1)]
         if args.workload == "large":
             other = "yee" if args.fields == "lattice" else "lattice"
             legs.append(({"yee": "standard PIC: levels from the Yee solver",
