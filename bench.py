@@ -195,10 +195,14 @@ class Pass:
     windows of S steps, each run stopping at its own step count)."""
 
     def __init__(self, wl, S, precision, binning, predictor=None, fields="lattice",
-                 occupancy=0, graph=False):
+                 occupancy=0, graph=False, reorder=False):
         from paper_2102_10983_amd import runner
         self.wl = wl
         self.graph = graph
+        # single runs in windows: re-order the groups before every window by
+        # the binning's score (learned, psi) or, for "persistence", by each
+        # particle's load in the previous window (a k trace of it)
+        self.reorder = reorder
         self.fill_events = []
         self.S = S
         self.binning = binning
@@ -229,6 +233,9 @@ class Pass:
         run, wl = self.run, self.wl
         run.reset()
         self.pusher.counters_reset()
+        if self.reorder and not self.batch:
+            self._windows_reordered(stream, events)
+            return
         if self.binning == "learned":
             self.predictor.prebin(self.pusher, self.a0, n=None if self.batch else 0,
                                   width=self.pb_width)
@@ -281,6 +288,44 @@ class Pass:
                 run.pusher.push(run.n, s)
             run.n += s
 
+    def _windows_reordered(self, stream, events):
+        import torch
+        from paper_2102_10983_amd import predictor as PR
+        run, wl = self.run, self.wl
+        buf = None
+        if self.binning == "persistence":
+            buf = torch.empty((self.S, wl.num), dtype=torch.int8, device="cuda")
+        prev = None
+        while run.n < wl.steps:
+            s = min(self.S, wl.steps - run.n)
+            if self.binning == "learned":
+                self.predictor.prebin(self.pusher, self.a0, n=run.n, width=self.pb_width)
+            elif self.binning == "psi":
+                score = PR.psi_score(self.pusher, self.a0, wl.dt, wl.psi_max, n=run.n)
+                self.pusher.prebin(score, nbuckets=1, width=self.pb_width)
+            elif self.binning == "last_k":
+                if run.n > 0:
+                    self.pusher.prebin(PR.last_k_score(self.pusher), nbuckets=1,
+                                       width=self.pb_width)
+            elif self.binning == "persistence":
+                if prev is not None:
+                    self.pusher.prebin(PR.persistence_score(buf[:prev]), nbuckets=1,
+                                       width=self.pb_width)
+                self.pusher.ktrace_set(buf[:s], run.n, 0)
+            run.fill(run.n, s)
+            e0 = torch.cuda.Event(enable_timing=True) if events is not None else None
+            e1 = torch.cuda.Event(enable_timing=True) if events is not None else None
+            if e0:
+                e0.record(stream)
+            run.pusher.push(run.n, s)
+            if e1:
+                e1.record(stream)
+                events.append((e0, e1))
+            run.n += s
+            prev = s
+        if buf is not None:
+            self.pusher.ktrace_set(None)
+
     def time(self, steps, warmup, stream, events=None):
         import torch
         for _ in range(warmup):
@@ -312,6 +357,10 @@ def make_workload(name: str, args):
         desc = (f"learned-binning workload: plane wave a0=150, {wl.num} electrons at rest over "
                 f"16 lambda, T/dt=75, dx=1.01 c dt, {wl.ncells} cells, {wl.steps} steps, "
                 f"order {wl.order}, psi_max {wl.psi_max}")
+    elif name == "stress20":
+        wl = W.stress_case(psi_max=0.01, num=1 << 20, periods=100.0, order=3)
+        desc = (f"plane wave a0=150, {wl.num} thermal (10 keV) electrons over 200 lambda, "
+                f"T/dt=75, {wl.ncells} cells, {wl.steps} steps, order 3, psi_max 0.01")
     elif name == "stress":
         wl = W.stress_case(psi_max=args.psi, num=args.num or (1 << 24), periods=args.periods,
                            order=args.order)
@@ -494,6 +543,17 @@ def main():
                                      "none", "lattice", 1))
                         legs.append((f"workload {name}, step-0 Psi order", name,
                                      args.precision, "psi", "lattice", 1))
+                    if name == "stress":
+                        for b, what in (("none", "position order"),
+                                        ("learned", "learned score before every window"),
+                                        ("psi", "step-0 Psi score before every window"),
+                                        ("last_k", "persistence: each particle's k at the "
+                                                   "end of the previous window"),
+                                        ("persistence", "persistence: each particle's load "
+                                                        "in the previous window (k trace)")):
+                            legs.append((f"2^20 thermal electrons in windows of 750 steps, {what}",
+                                         "stress20", args.precision, b, "lattice", 1, 750,
+                                         False, True))
                     if name == "batch":
                         legs.append(("workload batch in device-driven windows of 750 steps, "
                                      "the whole pass replayed from one HIP graph (rings of 753 "
@@ -502,6 +562,7 @@ def main():
         for leg_spec in legs:
             label, wname, prec, binning, fields, nsteps = leg_spec[:6]
             leg_S, leg_graph = (leg_spec[6], leg_spec[7]) if len(leg_spec) > 6 else (0, False)
+            leg_reorder = leg_spec[8] if len(leg_spec) > 8 else False
             if (wname == args.workload and prec == args.precision and binning == args.binning
                     and fields == args.fields):
                 continue
@@ -511,7 +572,8 @@ def main():
             lsteps = max(w.steps for w in lwl) if isinstance(lwl, list) else lwl.steps
             p = Pass(lwl, leg_S or (lsteps if args.S <= 0 else args.S), prec, binning,
                      model if binning == "learned" else None, fields,
-                     occupancy if prec == "fp64fast" else 0, graph=leg_graph)
+                     occupancy if prec == "fp64fast" else 0, graph=leg_graph,
+                     reorder=leg_reorder)
             p.pb_width = args.pb_width
             ev = []
             t = p.time(nsteps, 1, stream, ev)
@@ -519,6 +581,8 @@ def main():
             leg = {"label": label, "workload": ldesc if wname != args.workload else args.workload,
                    "precision": prec, "binning": binning, "fields": fields,
                    **({"steps_per_launch": leg_S, "hip_graph": True} if leg_graph else {}),
+                   **({"steps_per_launch": leg_S, "reordered_every_window": True}
+                      if leg_reorder else {}),
                    "steps": nsteps, "ms_per_step": t / nsteps * 1e3,
                    "value": c["sub_steps"] * nsteps / t,
                    "push_ms": sum(a.elapsed_time(b) for a, b in ev) / nsteps,

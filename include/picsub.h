@@ -379,6 +379,15 @@ pic_status pic_dephasing_read(pic_ctx *ctx, pic_mem mem, double *R0,
 pic_status pic_energy_read(pic_ctx *ctx, pic_mem mem, double *work,
                            double *err_max);
 
+/* Order score from a k trace (a persistence control for the predictor;
+ * ours): ktrace is a device int8 [steps][count] array as pic_ktrace_set
+ * records it (k per step, -1 where a particle was not live); score (device,
+ * count floats) gets, per column, log2 of the mean of 4^k over the live
+ * steps, NaN for a column with none (the lightest for pic_prebin).
+ * Asynchronous on hip_stream; PIC_E_ARG for null pointers or empty sizes. */
+pic_status pic_ktrace_load(const int8_t *ktrace, int32_t steps, int64_t count, float *score,
+                           void *hip_stream);
+
 /* Measurement aid, not part of the method: the attainable FP64 vector FMA
  * rate.  Launches `blocks` workgroups of 256 lanes on hip_stream; each lane
  * runs 16 independent FMA chains of `iters` rounds (2 * 16 * iters flop per

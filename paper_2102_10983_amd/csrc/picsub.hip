@@ -1307,6 +1307,15 @@ pic_status pic_energy_read(pic_ctx *ctx, pic_mem mem, double *work, double *err_
     return diag_out(ctx, mem, ctx->work, ctx->werr, work, err_max);
 }
 
+pic_status pic_ktrace_load(const int8_t *ktrace, int32_t steps, int64_t count, float *score,
+                           void *hip_stream)
+{
+    if (!ktrace || !score || steps < 1 || count < 1) return PIC_E_ARG;
+    ktrace_load_kernel<<<grid_for(count, 256, 8192), 256, 0, (hipStream_t)hip_stream>>>(
+        ktrace, steps, count, score);
+    return hipGetLastError() == hipSuccess ? PIC_OK : PIC_E_DEVICE;
+}
+
 pic_status pic_fma_probe(double *out, int32_t blocks, int64_t iters, void *hip_stream)
 {
     if (!out || blocks < 1 || iters < 1) return PIC_E_ARG;

@@ -341,6 +341,27 @@ __global__ void slots_to_caller_kernel(const int32_t *__restrict__ perm, int64_t
     }
 }
 
+// Order score from a k trace (persistence): per particle (column), log2 of
+// the mean of 4^k over the steps where it was live (k >= 0); NaN when it was
+// never live.  Columns are consecutive in memory across threads.
+__global__ void ktrace_load_kernel(const int8_t *__restrict__ kt, int32_t steps, int64_t count,
+                                   float *__restrict__ score)
+{
+    for (int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < count;
+         c += int64_t(gridDim.x) * blockDim.x) {
+        uint64_t tot = 0;
+        int32_t live = 0;
+        for (int32_t s = 0; s < steps; ++s) {
+            const int k = kt[int64_t(s) * count + c];
+            if (k >= 0) {
+                tot += uint64_t(1) << (2 * k);
+                ++live;
+            }
+        }
+        score[c] = live ? float(log2(double(tot) / double(live))) : __builtin_nanf("");
+    }
+}
+
 // Attainable FP64 vector rate on this device (a measurement aid, not part of
 // the method): every lane runs 16 independent chains of fused multiply-adds,
 // enough to cover the FMA latency, `iters` rounds each; the sums are stored

@@ -37,7 +37,7 @@ EXPORTS = ("pic_create", "pic_destroy", "pic_last_error", "pic_particles_set",
            "pic_mlp_grad", "pic_mlp_adam", "pic_prebin", "pic_state_export",
            "pic_state_import", "pic_fields_yee", "pic_fields_yee_r", "pic_fields_read",
            "pic_fields_read_r", "pic_diag_track", "pic_dephasing_read",
-           "pic_energy_read", "pic_gamma_max_read", "pic_fma_probe",
+           "pic_energy_read", "pic_gamma_max_read", "pic_fma_probe", "pic_ktrace_load",
            "pic_predictor_set", "pic_autotune_forget")
 
 MLP_FEATURES = 8
@@ -144,6 +144,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "pic_energy_read": ([vp, C.c_int, vp, vp], C.c_int),
         "pic_gamma_max_read": ([vp, C.c_int, vp], C.c_int),
         "pic_fma_probe": ([vp, i32, C.c_int64, vp], C.c_int),
+        "pic_ktrace_load": ([vp, i32, C.c_int64, vp, vp], C.c_int),
         "pic_predictor_set": ([vp, vp, vp, vp, C.c_float, i32], C.c_int),
         "pic_autotune_forget": ([], C.c_int),
         "pic_dephasing_read": ([vp, C.c_int, vp, vp], C.c_int),
@@ -579,6 +580,20 @@ def _stream_ptr():
 def _mlp_status(st: int, what: str):
     if st != 0:
         raise PicError(st, what)
+
+
+def ktrace_load(ktrace, out=None):
+    """Per-column log2 of the mean 4^k over the live steps of a k trace
+    (device int8 [steps, count]); a float32 tensor, on torch's current stream."""
+    torch = _torch()
+    L = load_library()
+    steps, count = ktrace.shape
+    if out is None:
+        out = torch.empty(count, dtype=torch.float32, device="cuda")
+    _mlp_status(L.pic_ktrace_load(_dev_ptr(ktrace, torch.int8, steps * count), int(steps),
+                                  int(count), _dev_ptr(out, torch.float32, count), _stream_ptr()),
+                "ktrace load")
+    return out
 
 
 def fma_probe(blocks: int, iters: int):

@@ -105,6 +105,25 @@ def psi_score(pusher: picsub.Pusher, a0, dt: float, psi_max: float, n=None):
     return torch.clamp(torch.log2(psi0 / psi_max), min=0.0).float().contiguous()
 
 
+def persistence_score(ktrace):
+    """Order score from the previous window (persistence): log2 of a
+    particle's mean sub-steps per step over the steps of a k trace (device
+    int8 [steps, particles], caller order, -1 where not live), by the
+    library's reduction kernel; NaN (lightest) for particles with no live
+    step."""
+    return picsub.ktrace_load(ktrace)
+
+
+def last_k_score(pusher):
+    """Order score from the last step alone (persistence at no recording
+    cost): each particle's k at its last step, from the state (caller
+    order); -1 (lightest) for particles not live."""
+    import torch
+    k = torch.empty(pusher.num, dtype=torch.int8, device="cuda")
+    pusher.diag_device({"k_last": k})
+    return k.float().contiguous()
+
+
 # -- training data -----------------------------------------------------------
 def traced_load(run, steps: int, chunk: int = 500):
     """Run `steps` steps from the current state with a k trace of every
