@@ -400,6 +400,35 @@ pic_status pic_fma_probe(double *out, int32_t blocks, int64_t iters, void *hip_s
  * (np doubles, caller order), as pic_dephasing_read. */
 pic_status pic_gamma_max_read(pic_ctx *ctx, pic_mem mem, double *gmax);
 
+/* The energy error of Sec. IV, Eq. (gamma error): the running maximum over
+ * completed steps of |gamma - gamma_th| / gamma_th, gamma_th = 1 + (a - a_i)^2 / 2
+ * (Eq. (theoretical gamma): the plane-wave solution of an electron that started
+ * at rest where the vector potential was a_i).  a is taken at the phase of the
+ * momentum, which lags x by half of the step's last sub-step: time
+ * (n + 1) dt - dt* / 2 and position x - v_x dt* / 2, with u = (x - x_origin)/dx - 1/2
+ * its E-node coordinate; a is linear between the points of a potential table
+ * on a phase lattice like the field table's: entry (A tau + B u + C) mod M at
+ * time tau dt.  Computed by every push while the trajectory diagnostics are on.
+ *
+ * pic_gamma_error_lattice: the potential table of a run (atab: device, M
+ * doubles, owned by the caller, kept alive while attached; strict mode checks
+ * it is finite) and its lattice; a grid shift moves C by B per cell, so a
+ * moving-grid caller sets the lattice again with its fields.  No reset of the
+ * maxima.  A null atab detaches (that run's maxima stay as they are).
+ * PIC_E_ARG for a bad run or M <= 0.
+ *
+ * pic_gamma_error_start: a_i of every particle (np doubles, caller order,
+ * host or device, copied) and the maxima set to 0; needs particles loaded
+ * and the diagnostics on (PIC_E_STATE otherwise).  New particles
+ * (pic_particles_set) or pic_diag_track(ctx, 1) stop it until the next start.
+ *
+ * pic_gamma_error_read: the maxima (np doubles, caller order), as
+ * pic_dephasing_read; PIC_E_ARG ("no such diagnostic") when not started. */
+pic_status pic_gamma_error_lattice(pic_ctx *ctx, int32_t run, const double *atab, int64_t M,
+                                   int64_t A, int64_t B, int64_t C);
+pic_status pic_gamma_error_start(pic_ctx *ctx, pic_mem mem, const double *ai);
+pic_status pic_gamma_error_read(pic_ctx *ctx, pic_mem mem, double *emax);
+
 /* ------------------------------------------------------------------ */
 /* Launch shape.  None of these knobs changes a result: every kernel    */
 /* gives each particle the same arithmetic whichever lane runs it.      */

@@ -34,6 +34,8 @@ struct RunDesc {
     int64_t n_cur;                    // current level in device-driven mode
     int64_t n_stop;                   // device-driven mode: no step starts at or past this level
     int64_t M, aE, bE, cE, aB, bB, cB;
+    const double *atab;               // potential a on a phase lattice (null: no energy error)
+    int64_t atM, atA, atB, atC;       //   entry (atA tau + atB u + atC) mod atM
     int32_t D, ncells, kmax, margin;
 };
 
@@ -52,6 +54,8 @@ struct PushArgs {
     double *rmax;                     //   the start, running max of |R - R0| / R0,
     double *work, *werr;              //   work of E since the start, largest step energy error,
     double *gmax;                     //   largest gamma after a completed step
+    const double *ai;                 // energy error (null: off): a at the start, running
+    double *emax;                     //   max of |gamma - gamma_th| / gamma_th
     uint64_t *cnt;                    // [nruns][NSLOT][NCNT]
     int64_t kt_n0, kt_first, kt_count;
     int64_t n0;                       // NO_LEVEL: every run starts at its n_cur
@@ -295,6 +299,29 @@ __device__ __forceinline__ void dephasing_update(double &rmax, double &gmax, dou
     const double d = fabs((g - px) - r0) / r0;
     rmax = d > rmax ? d : rmax;
     gmax = g > gmax ? g : gmax;
+}
+
+// After a completed step: the running maximum of the energy error
+// |gamma - gamma_th| / gamma_th (Eq. (gamma error)) against the plane-wave
+// solution gamma_th = 1 + (a - a_i)^2 / 2 (Eq. (theoretical gamma)) of an
+// electron that started at rest where the potential was a_i.  a is taken at
+// the phase of the momentum, which lags x by half of the step's last sub-step
+// (time tau = n + 1 - dt*/(2 dt) in steps, E-node coordinate u at x - v_x dt*/2)
+// and is linear between the points of the run's potential lattice.  The order
+// of operations is that of a CPU loop.
+__device__ __forceinline__ void gamma_error_update(double &emax, const RunDesc &R, double tau,
+                                                   double u, double g, double ai)
+{
+    const double m = double(R.atA) * tau + double(R.atB) * u + double(R.atC);
+    const double mf = floor(m);
+    int64_t j0 = int64_t(mf) % R.atM;
+    if (j0 < 0) j0 += R.atM;
+    const int64_t j1 = j0 + 1 == R.atM ? 0 : j0 + 1;
+    const double av = R.atab[j0] + (m - mf) * (R.atab[j1] - R.atab[j0]);
+    const double d = av - ai;
+    const double gth = 1.0 + 0.5 * (d * d);
+    const double e = fabs(g - gth) / gth;
+    emax = e > emax ? e : emax;
 }
 
 // Energy accounting (App. B): the work of E over a sub-step is

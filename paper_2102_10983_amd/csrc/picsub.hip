@@ -56,6 +56,8 @@ struct RunHost {
     bool driven = false;         // device-driven source set
     const double *table = nullptr;
     int64_t M = 0, co[6] = {0, 0, 0, 0, 0, 0};
+    const double *atab = nullptr;   // potential lattice of the energy error (caller's memory)
+    int64_t at[4] = {0, 0, 0, 0};   // its M, A, B, C
     int64_t n_dev = 0;           // level the device-driven counter reaches after queued work
     int64_t n_stop = INT64_MAX;  // device-driven stop level
     double x_origin0 = 0.0;      // x_origin at creation; the grid sits shift cells from it
@@ -129,6 +131,11 @@ struct pic_ctx {
     // trajectory diagnostics (allocated when first switched on)
     double *r0 = nullptr, *rmax = nullptr, *work = nullptr, *werr = nullptr, *gmax = nullptr;
     bool deph = false;
+    // energy error against the plane-wave solution: a_i and the running
+    // maximum per slot (allocated at the first start; gerr: started for the
+    // particles loaded now)
+    double *ai = nullptr, *emax = nullptr;
+    bool gerr = false;
     // k trace
     int8_t *ktrace = nullptr;
     int64_t kt_n0 = 0, kt_first = 0, kt_count = 0;
@@ -195,7 +202,7 @@ void free_all(pic_ctx *c)
     void *ptrs[] = {c->x, c->px, c->py, c->pz, c->kold, c->status, c->perm, c->key,
                     c->d_runs, c->group_run, c->group_order, c->group_prio, c->wtab, c->cnt,
                     c->r0, c->rmax, c->work, c->werr, c->gmax, c->pred_w, c->pred_norm, c->pred_feat,
-                    c->pred_score, c->d_flag};
+                    c->pred_score, c->d_flag, c->ai, c->emax};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (RunHost &r : c->runs) {
@@ -212,6 +219,8 @@ void free_all(pic_ctx *c)
     c->cnt = nullptr;
     c->r0 = c->rmax = c->work = c->werr = c->gmax = nullptr;
     c->deph = false;
+    c->ai = c->emax = nullptr;
+    c->gerr = false;
     c->pred_w = nullptr;
     c->pred_norm = c->pred_feat = c->pred_score = nullptr;
     c->pred_every = 0;
@@ -304,6 +313,11 @@ RunDesc make_desc(const RunHost &r)
     d.aB = r.co[3];
     d.bB = r.co[4];
     d.cB = r.co[5];
+    d.atab = r.atab;
+    d.atM = r.at[0];
+    d.atA = r.at[1];
+    d.atB = r.at[2];
+    d.atC = r.at[3];
     d.D = r.prm.ring_depth;
     d.ncells = r.prm.ncells;
     d.kmax = r.prm.k_max;
@@ -342,6 +356,8 @@ PushArgs push_args(pic_ctx *ctx, int64_t n0, int32_t S)
     a.work = ctx->deph ? ctx->work : nullptr;
     a.werr = ctx->deph ? ctx->werr : nullptr;
     a.gmax = ctx->deph ? ctx->gmax : nullptr;
+    a.ai = ctx->deph && ctx->gerr ? ctx->ai : nullptr;
+    a.emax = ctx->deph && ctx->gerr ? ctx->emax : nullptr;
     a.cnt = ctx->cnt;
     a.kt_n0 = ctx->kt_n0;
     a.kt_first = ctx->kt_first;
@@ -737,6 +753,7 @@ pic_status load_particles(pic_ctx *ctx, pic_mem mem, const double *x, const doub
                            ctx->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     }
+    ctx->gerr = false;                            // new particles: no a_i for them yet
     if (e == hipSuccess && ctx->r0) {            // new particles: the diagnostics restart
                                                   // (their values belong to slots)
         diag_init_kernel<<<grid_for(ctx->slots, 256, 8192), 256, 0, ctx->stream>>>(
@@ -1255,6 +1272,7 @@ pic_status pic_diag_track(pic_ctx *ctx, int32_t on)
         ctx->gmax);
     LAUNCH_CHECK(ctx);
     ctx->deph = true;
+    ctx->gerr = false;
     return PIC_OK;
 }
 
@@ -1328,6 +1346,76 @@ pic_status pic_gamma_max_read(pic_ctx *ctx, pic_mem mem, double *gmax)
 {
     if (!ctx) return PIC_E_ARG;
     return diag_out(ctx, mem, ctx->gmax, nullptr, gmax, nullptr);
+}
+
+pic_status pic_gamma_error_lattice(pic_ctx *ctx, int32_t run, const double *atab, int64_t M,
+                                   int64_t A, int64_t B, int64_t C)
+{
+    CTX_CHECK(ctx);
+    if (run < 0 || run >= ctx->nruns) return fail(ctx, PIC_E_ARG, "bad run %d", run);
+    RunHost &R = ctx->runs[size_t(run)];
+    if (!atab) {
+        R.atab = nullptr;
+        std::fill(R.at, R.at + 4, int64_t(0));
+        return upload_desc(ctx, run);
+    }
+    if (M <= 0) return fail(ctx, PIC_E_ARG, "bad potential lattice size");
+    if (pic_status fs = check_finite(ctx, PIC_MEM_DEVICE, atab, M, "the potential table")) return fs;
+    R.atab = atab;
+    const int64_t at[4] = {M, A, B, C};
+    std::copy(at, at + 4, R.at);
+    return upload_desc(ctx, run);
+}
+
+pic_status pic_gamma_error_start(pic_ctx *ctx, pic_mem mem, const double *ai)
+{
+    CTX_CHECK(ctx);
+    if (mem != PIC_MEM_HOST && mem != PIC_MEM_DEVICE) return fail(ctx, PIC_E_ARG, "bad pic_mem");
+    if (!ai) return fail(ctx, PIC_E_ARG, "null a_i");
+    if (!ctx->have_particles) return fail(ctx, PIC_E_STATE, "no particles loaded");
+    if (!ctx->r0 || !ctx->deph)
+        return fail(ctx, PIC_E_STATE, "the trajectory diagnostics are off (pic_diag_track)");
+    const size_t n = size_t(ctx->np);
+    if (pic_status fs = check_finite(ctx, mem, ai, int64_t(n), "a_i")) return fs;
+    const size_t slots = size_t(ctx->slots);
+    if (!ctx->ai) {
+        pic_status st;
+        if ((st = dev_alloc(ctx, &ctx->ai, slots)) || (st = dev_alloc(ctx, &ctx->emax, slots))) {
+            if (ctx->ai) (void)hipFree(ctx->ai);
+            if (ctx->emax) (void)hipFree(ctx->emax);
+            ctx->ai = ctx->emax = nullptr;
+            return st;
+        }
+    }
+    const double *src = ai;
+    double *tmp = nullptr;
+    if (mem == PIC_MEM_HOST && n) {
+        if (pic_status st = dev_alloc(ctx, &tmp, n)) return st;
+        const hipError_t e = hipMemcpyAsync(tmp, ai, n * 8, hipMemcpyHostToDevice, ctx->stream);
+        if (e != hipSuccess) {
+            (void)hipStreamSynchronize(ctx->stream);
+            (void)hipFree(tmp);
+            return fail(ctx, PIC_E_DEVICE, "a_i copy: %s", hipGetErrorString(e));
+        }
+        src = tmp;
+    }
+    gerr_init_kernel<<<grid_for(ctx->slots, 256, 8192), 256, 0, ctx->stream>>>(
+        ctx->perm, ctx->slots, src, ctx->ai, ctx->emax);
+    hipError_t e = hipGetLastError();
+    if (tmp) {
+        const hipError_t e2 = hipStreamSynchronize(ctx->stream);
+        (void)hipFree(tmp);
+        if (e == hipSuccess) e = e2;
+    }
+    if (e != hipSuccess) return fail(ctx, PIC_E_DEVICE, "energy error start: %s", hipGetErrorString(e));
+    ctx->gerr = true;
+    return PIC_OK;
+}
+
+pic_status pic_gamma_error_read(pic_ctx *ctx, pic_mem mem, double *emax)
+{
+    if (!ctx) return PIC_E_ARG;
+    return diag_out(ctx, mem, ctx->gerr ? ctx->emax : nullptr, nullptr, emax, nullptr);
 }
 
 pic_status pic_tune_set(pic_ctx *ctx, const pic_tune *t)
@@ -1721,6 +1809,17 @@ pic_status pic_prebin(pic_ctx *ctx, const float *score, int32_t nbuckets, float 
             }
             if (e == hipSuccess)
                 e = hipMemcpyAsync(ctx->gmax, nsoa, n * 8, hipMemcpyDeviceToDevice, ctx->stream);
+            if (e == hipSuccess && ctx->gerr) {
+                double *d2[2] = {ctx->ai, ctx->emax};
+                for (int a = 0; a < 2 && e == hipSuccess; ++a)
+                    e = hipMemcpyAsync(nsoa + a * n, d2[a], n * 8, hipMemcpyDeviceToDevice,
+                                       ctx->stream);
+                if (e == hipSuccess) {
+                    permute_pair_kernel<<<grid_for(slots, 256, 8192), 256, 0, ctx->stream>>>(
+                        dest, slots, ctx->perm, nsoa, nsoa + n, ctx->ai, ctx->emax);
+                    e = hipGetLastError();
+                }
+            }
         }
         if (e == hipSuccess)
             e = hipMemcpyAsync(ctx->perm, nperm, n * 4, hipMemcpyDeviceToDevice, ctx->stream);

@@ -107,6 +107,12 @@ __global__ void __launch_bounds__(64 * WPG) push_wave_fp32c_kernel(PushArgs a)
         wacc = a.work[s];
         wem = a.werr[s];
     }
+    const bool gerr = deph && a.emax != nullptr && R.atab != nullptr;   // energy error
+    double aiv = 0.0, emx = 0.0;
+    if (gerr && mine) {
+        aiv = a.ai[s];
+        emx = a.emax[s];
+    }
     if (mine) {
         const double xi = (a.x[s] - R.x_origin) / R.dx;
         status = a.status[s];
@@ -349,6 +355,13 @@ __global__ void __launch_bounds__(64 * WPG) push_wave_fp32c_kernel(PushArgs a)
             const double qz = double(pzh) + double(pzl);
             dephasing_update(rmx, gmx, r0v, qx, qy, qz);
             energy_close(wacc, wem, gst, gamma_of(qx, qy, qz), sw);
+            if (gerr) {
+                const double g = gamma_of(qx, qy, qz);
+                const double half = 0.5 * ldexp(1.0, -2 * k);      // dt* / 2, in dt
+                const double xi = double(cell) + (double(fr) + double(frc));
+                gamma_error_update(emx, R, double(n + 1) - half,
+                                   xi - half * R.dtdx * (qx / g) - 0.5, g, aiv);
+            }
         }
     }
     if (mine) {
@@ -358,6 +371,7 @@ __global__ void __launch_bounds__(64 * WPG) push_wave_fp32c_kernel(PushArgs a)
             a.work[s] = wacc;
             a.werr[s] = wem;
         }
+        if (gerr) a.emax[s] = emx;
         if (moved) {
             const double xi = double(cell) + (double(fr) + double(frc));
             a.x[s] = R.x_origin + xi * R.dx;

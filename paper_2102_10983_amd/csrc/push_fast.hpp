@@ -328,6 +328,12 @@ __global__ void __launch_bounds__(64 * WPG)
         wacc = a.work[s];
         wem = a.werr[s];
     }
+    const bool gerr = deph && a.emax != nullptr && RD.atab != nullptr;   // energy error
+    double aiv = 0.0, emx = 0.0;
+    if (gerr && mine) {
+        aiv = a.ai[s];
+        emx = a.emax[s];
+    }
     // launch steps whose k is recorded: [kt_lo, kt_hi)
     int kt_lo = 0, kt_hi = 0;
     if (tracing) {
@@ -595,6 +601,12 @@ __global__ void __launch_bounds__(64 * WPG)
         if (deph && done) {
             dephasing_update(rmx, gmx, r0v, px, py, pz);
             energy_close(wacc, wem, gst, gamma_of(px, py, pz), swork);
+            if (gerr) {
+                const double g = gamma_of(px, py, pz);
+                const double half = 0.5 * ldexp(1.0, -2 * k);      // dt* / 2, in dt
+                gamma_error_update(emx, RD, double(n + 1) - half,
+                                   x - half * dtdx * (px / g) - 0.5, g, aiv);
+            }
         }
 
         // hand the step-ahead window to LDS for the next step
@@ -627,6 +639,7 @@ __global__ void __launch_bounds__(64 * WPG)
             a.work[s] = wacc;
             a.werr[s] = wem;
         }
+        if (gerr) a.emax[s] = emx;
     }
     uint64_t *slot = a.cnt + (int64_t(run) * NSLOT + pos % NSLOT) * NCNT;
     if (lane >= 1 && lane <= PIC_K_MAX_LIMIT) {

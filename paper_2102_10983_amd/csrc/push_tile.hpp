@@ -74,6 +74,19 @@ __global__ void __launch_bounds__(TILE) push_tile_kernel(PushArgs a)
         wacc = a.work[i];
         wem = a.werr[i];
     }
+    const bool gerr = deph && a.emax != nullptr && R.atab != nullptr;   // energy error
+    double aiv = 0.0, emx = 0.0;
+    if (gerr && mine) {
+        aiv = a.ai[i];
+        emx = a.emax[i];
+    }
+    // the energy error after a completed step of level n at level k
+    auto gerr_step = [&](int64_t n, int k) {
+        const double g = gamma_of(px, py, pz);
+        const double half = 0.5 * ldexp(1.0, -2 * k);      // dt* / 2, in dt
+        const double xp = x - half * R.dt * (px / g);
+        gamma_error_update(emx, R, double(n + 1) - half, (xp - R.x_origin) / R.dx - 0.5, g, aiv);
+    };
     if (mine) {
         x = a.x[i];
         px = a.px[i];
@@ -200,6 +213,7 @@ __global__ void __launch_bounds__(TILE) push_tile_kernel(PushArgs a)
                     dephasing_update(rmx, gmx, r0v, px, py, pz);
                     energy_close(wacc, wem, g0, gamma_of(px, py, pz),
                                  sub_step_work((0.5 * R.qm) * (0.5 * (dto + R.dt)), E, vb, py / g2));
+                    if (gerr) gerr_step(n, 0);
                 }
             } else {
                 heavy = true;
@@ -301,6 +315,7 @@ __global__ void __launch_bounds__(TILE) push_tile_kernel(PushArgs a)
                     if (deph) {
                         dephasing_update(rmx, gmx, r0v, px, py, pz);
                         energy_close(wacc, wem, gst, gamma_of(px, py, pz), swk[t]);
+                        if (gerr) gerr_step(n, k);
                     }
                 } else {
                     status = PIC_PARTICLE_LOST;
@@ -323,6 +338,7 @@ __global__ void __launch_bounds__(TILE) push_tile_kernel(PushArgs a)
             a.work[i] = wacc;
             a.werr[i] = wem;
         }
+        if (gerr) a.emax[i] = emx;
     }
     flush_wave(cnt, a.cnt + (int64_t(run) * NSLOT + blockIdx.x % NSLOT) * NCNT, lane);
 }

@@ -77,6 +77,12 @@ __global__ void __launch_bounds__(64 * WPG) push_wave_kernel(PushArgs a)
         wacc = a.work[s];
         wem = a.werr[s];
     }
+    const bool gerr = deph && a.emax != nullptr && R.atab != nullptr;   // energy error
+    double aiv = 0.0, emx = 0.0;
+    if (gerr && mine) {
+        aiv = a.ai[s];
+        emx = a.emax[s];
+    }
 
     const int S_run = run_steps(a, R, n0);
     for (int st = 0; st < S_run; ++st) {
@@ -221,6 +227,13 @@ __global__ void __launch_bounds__(64 * WPG) push_wave_kernel(PushArgs a)
         if (deph && done) {
             dephasing_update(rmx, gmx, r0v, px, py, pz);
             energy_close(wacc, wem, gst, gamma_of(px, py, pz), sw);
+            if (gerr) {
+                const double g = gamma_of(px, py, pz);
+                const double half = 0.5 * ldexp(1.0, -2 * k);      // dt* / 2, in dt
+                const double xp = x - half * R.dt * (px / g);
+                gamma_error_update(emx, R, double(n + 1) - half, (xp - R.x_origin) / R.dx - 0.5,
+                                   g, aiv);
+            }
         }
     }
     if (mine) {
@@ -238,6 +251,7 @@ __global__ void __launch_bounds__(64 * WPG) push_wave_kernel(PushArgs a)
             a.work[s] = wacc;
             a.werr[s] = wem;
         }
+        if (gerr) a.emax[s] = emx;
     }
     cnt.flush(a.cnt + (int64_t(run) * NSLOT + pos % NSLOT) * NCNT, lane);
 }

@@ -325,6 +325,19 @@ __global__ void diag_init_kernel(int64_t slots, const double *__restrict__ px,
     }
 }
 
+// Energy error start: a_i from caller order into slots, running maxima 0.
+__global__ void gerr_init_kernel(const int32_t *__restrict__ perm, int64_t slots,
+                                 const double *__restrict__ ai_caller, double *__restrict__ ai,
+                                 double *__restrict__ emax)
+{
+    for (int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; s < slots;
+         s += int64_t(gridDim.x) * blockDim.x) {
+        const int32_t u = perm[s];
+        ai[s] = u >= 0 ? ai_caller[u] : 0.0;
+        emax[s] = 0.0;
+    }
+}
+
 // Two per-slot arrays in caller order (an output, or the array it would
 // come from, may be null: that output is skipped).
 __global__ void slots_to_caller_kernel(const int32_t *__restrict__ perm, int64_t slots,

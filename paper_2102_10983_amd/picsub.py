@@ -38,6 +38,7 @@ EXPORTS = ("pic_create", "pic_destroy", "pic_last_error", "pic_particles_set",
            "pic_state_import", "pic_fields_yee", "pic_fields_yee_r", "pic_fields_read",
            "pic_fields_read_r", "pic_diag_track", "pic_dephasing_read",
            "pic_energy_read", "pic_gamma_max_read", "pic_fma_probe", "pic_ktrace_load",
+           "pic_gamma_error_lattice", "pic_gamma_error_start", "pic_gamma_error_read",
            "pic_predictor_set", "pic_autotune_forget")
 
 MLP_FEATURES = 8
@@ -143,6 +144,10 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "pic_diag_track": ([vp, i32], C.c_int),
         "pic_energy_read": ([vp, C.c_int, vp, vp], C.c_int),
         "pic_gamma_max_read": ([vp, C.c_int, vp], C.c_int),
+        "pic_gamma_error_lattice": ([vp, i32, vp, C.c_int64, C.c_int64, C.c_int64, C.c_int64],
+                                    C.c_int),
+        "pic_gamma_error_start": ([vp, C.c_int, vp], C.c_int),
+        "pic_gamma_error_read": ([vp, C.c_int, vp], C.c_int),
         "pic_fma_probe": ([vp, i32, C.c_int64, vp], C.c_int),
         "pic_ktrace_load": ([vp, i32, C.c_int64, vp, vp], C.c_int),
         "pic_predictor_set": ([vp, vp, vp, vp, C.c_float, i32], C.c_int),
@@ -369,6 +374,33 @@ class Pusher:
         g = np.empty(self.num)
         self._check(self._lib.pic_gamma_max_read(self._ctx, MEM_HOST, g.ctypes.data))
         return g
+
+    def gamma_error_lattice(self, atab, M: int, coeffs, run: int = 0):
+        """Attach the potential table (FP64 device tensor on the phase lattice
+        coeffs = (A, B, C) of the E field) for the energy error; None detaches."""
+        torch = _torch()
+        if atab is None:
+            self._check(self._lib.pic_gamma_error_lattice(self._ctx, run, None, 0, 0, 0, 0))
+            self._keep_atab = None
+            return
+        A, B, Cc = (int(v) for v in coeffs[:3])
+        self._check(self._lib.pic_gamma_error_lattice(
+            self._ctx, run, _dev_ptr(atab, torch.float64, int(M) if M > 0 else None), int(M),
+            A, B, Cc))
+        self._keep_atab = atab
+
+    def gamma_error_start(self, ai):
+        """a_i of every particle (host array, caller order); maxima to 0."""
+        ai = np.ascontiguousarray(ai, dtype=np.float64)
+        if ai.size != self.num:
+            raise ValueError("a_i needs one value per particle")
+        self._check(self._lib.pic_gamma_error_start(self._ctx, MEM_HOST, ai.ctypes.data))
+
+    def gamma_error_read(self):
+        """Running maximum of |gamma - gamma_th| / gamma_th per particle."""
+        e = np.empty(self.num)
+        self._check(self._lib.pic_gamma_error_read(self._ctx, MEM_HOST, e.ctypes.data))
+        return e
 
     def push(self, n: int, S: int = 1):
         self._check(self._lib.pic_push_subcycled(self._ctx, n, S))

@@ -149,10 +149,13 @@ class PulseRun:
     Records, for the caller: the shift and length of every launch (so that a
     reference can repeat the same grids) and, through the trajectory
     diagnostics, the running maxima of |R - 1| (the dephasing error of
-    Sec. IV, Eq. (R error)) and of gamma (the peak energy of Sec. IV)."""
+    Sec. IV, Eq. (R error)), of gamma (the peak energy of Sec. IV) and, with
+    energy=True, of the energy error of Eq. (gamma error) against the
+    plane-wave solution (the potential table of the same lattice, a_i at each
+    electron's phase half a step before the start)."""
 
     def __init__(self, wl: W.Workload, *, S: int = 1000, precision: str = "fp64fast",
-                 k_max: int = 12, left: int = 8, stream=None):
+                 k_max: int = 12, left: int = 8, stream=None, energy: bool = False):
         import torch
         if wl.kind != "gauss":
             raise ValueError("PulseRun drives the Gaussian pulse workload")
@@ -166,6 +169,19 @@ class PulseRun:
         self.M = int(M)
         self.coeffs = W.shifted_coeffs(wl.lat, shift)
         self.table = torch.from_numpy(np.ascontiguousarray(table)).to("cuda")
+        self.energy = bool(energy)
+        if self.energy:
+            atab, aM, ashift = wl.potential()
+            if aM != self.M or ashift != shift:
+                raise ValueError("the potential table must share the field table's lattice")
+            self.atab = torch.from_numpy(np.ascontiguousarray(atab)).to("cuda")
+            aE, bE, cE = self.coeffs[:3]
+            # a at tau = -1/2 (the phase of the zero momentum) at each start
+            m = aE * -0.5 + bE * ((wl.x0 - wl.x_origin) / wl.dx - 0.5) + cE
+            mf = np.floor(m)
+            j0 = mf.astype(np.int64) % aM
+            j1 = (j0 + 1) % aM
+            self.ai = atab[j0] + (m - mf) * (atab[j1] - atab[j0])
         self.pusher = picsub.Pusher(num=wl.num, ncells=wl.ncells, order=wl.order, dx=wl.dx,
                                     dt=wl.dt, psi_max=wl.psi_max, x_origin=wl.x_origin,
                                     k_max=k_max, ring_depth=self.S + wl.order,
@@ -181,6 +197,8 @@ class PulseRun:
             self.shift = 0
         self.pusher.particles_set(self.wl.x0, *self.wl.p0)
         self.pusher.diag_track(True)
+        if self.energy:
+            self.pusher.gamma_error_start(self.ai)
         self.n = 0
         self.windows = []
 
@@ -201,6 +219,8 @@ class PulseRun:
         co = (aE, bE, cE + bE * self.shift, aB, bB, cB + bB * self.shift)
         p = wl.order
         self.pusher.fields_load_lattice(self.n - p, p + self.S, self.table, self.M, co)
+        if self.energy:
+            self.pusher.gamma_error_lattice(self.atab, self.M, co[:3])
         self.pusher.push(self.n, self.S)
         self.windows.append((self.n, self.S, self.shift))
         self.n += self.S
@@ -214,9 +234,12 @@ class PulseRun:
     def results(self) -> dict:
         d = self.pusher.diag()
         r0, rmax = self.pusher.dephasing_read()
-        return {"diag": d, "eps_dephasing": rmax, "R0": r0,
-                "gamma_max": self.pusher.gamma_max_read(),
-                "steps": self.n, "windows": list(self.windows)}
+        out = {"diag": d, "eps_dephasing": rmax, "R0": r0,
+               "gamma_max": self.pusher.gamma_max_read(),
+               "steps": self.n, "windows": list(self.windows)}
+        if self.energy:
+            out["eps_energy"] = self.pusher.gamma_error_read()
+        return out
 
     def close(self):
         self.pusher.close()

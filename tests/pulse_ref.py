@@ -21,11 +21,11 @@ from paper_2102_10983_amd import workloads as W
 XI_END = W.GAUSS_XI0 + 7.0 * W.GAUSS_SIGMA
 
 
-def _fields(wl, shift=0):
+def _fields(wl, shift=0, atab=None):
     table, M, tshift = wl.table()
     aE, bE, cE, aB, bB, cB = W.shifted_coeffs(wl.lat, tshift)
     return O.FieldSource(table=table, M=M,
-                         coeffs=(aE, bE, cE + bE * shift, aB, bB, cB + bB * shift))
+                         coeffs=(aE, bE, cE + bE * shift, aB, bB, cB + bB * shift), atab=atab)
 
 
 def _gamma_c(st):
@@ -78,28 +78,35 @@ def run_whole(wl, chunk: int = 20000, k_max: int = 12, max_steps: int = 1 << 28,
     return st, cnt, rmax, gmax
 
 
-def run_windows(wl, windows, k_max: int = 12, forced_k=None, gamma_max: bool = False):
+def run_windows(wl, windows, k_max: int = 12, forced_k=None, gamma_max: bool = False,
+                energy: bool = False):
     """The oracle over the launches of a device run (n, steps, shift).
     forced_k: optional [total steps, num] int8 array replacing the decision.
-    gamma_max: also return the running maximum of gamma (after each step)."""
+    gamma_max: also return the running maximum of gamma (after each step).
+    energy: also return the running maximum of the energy error (last)."""
     st = O.State(wl.x0, *wl.p0)
     r0 = O.dephasing_R(st.px, st.py, st.pz)
     rmax = np.zeros(wl.num)
     gmax = _gamma_c(st) if gamma_max else None
+    ai = emax = atab = None
+    if energy:
+        _, M, tshift = wl.table()
+        atab, _, _ = wl.potential()
+        ai = a_on_lattice(wl, atab, M, W.shifted_coeffs(wl.lat, tshift), -0.5, wl.x0)
+        emax = np.zeros(wl.num)
     cnt = O.Counters()
     ktrace = []
     for n, steps, shift in windows:
         prm = O.make_params(wl.ncells, wl.order, wl.dx, wl.dt, wl.psi_max,
                             wl.x_origin + shift * wl.dx, k_max=k_max)
         fk = None if forced_k is None else np.ascontiguousarray(forced_k[n:n + steps])
-        kt, pt = O.push(prm, _fields(wl, shift), st, n, steps, counters=cnt, r0=r0, rmax=rmax,
-                        gmax=gmax, trace=True, psi_trace=True, forced_k=fk)
+        kt, pt = O.push(prm, _fields(wl, shift, atab), st, n, steps, counters=cnt, r0=r0,
+                        rmax=rmax, gmax=gmax, trace=True, psi_trace=True, forced_k=fk, ai=ai,
+                        emax=emax)
         ktrace.append((kt, pt))
     kt = np.concatenate([k for k, _ in ktrace]) if ktrace else np.zeros((0, wl.num), np.int8)
     pt = np.concatenate([p for _, p in ktrace]) if ktrace else np.zeros((0, wl.num))
-    if gamma_max:
-        return st, cnt, rmax, kt, pt, gmax
-    return st, cnt, rmax, kt, pt
+    return (st, cnt, rmax, kt, pt) + ((gmax,) if gamma_max else ()) + ((emax,) if energy else ())
 
 
 def moving_windows(wl, S: int = 1000, left: int = 8, k_max: int = 12):
