@@ -1387,9 +1387,13 @@ pic_status pic_gamma_error_start(pic_ctx *ctx, pic_mem mem, const double *ai)
             return st;
         }
     }
+    if (n == 0) {                                  // no particles: nothing to start
+        ctx->gerr = true;
+        return PIC_OK;
+    }
     const double *src = ai;
     double *tmp = nullptr;
-    if (mem == PIC_MEM_HOST && n) {
+    if (mem == PIC_MEM_HOST) {
         if (pic_status st = dev_alloc(ctx, &tmp, n)) return st;
         const hipError_t e = hipMemcpyAsync(tmp, ai, n * 8, hipMemcpyHostToDevice, ctx->stream);
         if (e != hipSuccess) {
