@@ -138,6 +138,27 @@ class BatchRun:
         self.pusher.close()
 
 
+def initial_potential(wl: W.Workload, atab, M: int, coeffs):
+    """a_i of every electron of a pulse workload: the potential at its start
+    position half a step before the start (the time of its zero momentum),
+    linear between the points of the potential lattice (A, B, C) = coeffs[:3]."""
+    A, B, Cc = coeffs[:3]
+    m = A * -0.5 + B * ((wl.x0 - wl.x_origin) / wl.dx - 0.5) + Cc
+    mf = np.floor(m)
+    j0 = mf.astype(np.int64) % M
+    j1 = (j0 + 1) % M
+    return atab[j0] + (m - mf) * (atab[j1] - atab[j0])
+
+
+def pulse_passed(wl: W.Workload, n: int, x, status) -> bool:
+    """True once no electron is live or the pulse (phase t - x) has passed
+    every live one: the end of a model-problem run."""
+    live = status == 0
+    if not live.any():
+        return True
+    return bool(np.all(n * wl.dt - x[live] > W.GAUSS_XI0 + 7.0 * W.GAUSS_SIGMA))
+
+
 class PulseRun:
     """Electrons in the Gaussian pulse of the paper's model problem (Sec. II),
     pushed in launches of S steps on a grid of wl.ncells nodes that moves with
@@ -175,13 +196,7 @@ class PulseRun:
             if aM != self.M or ashift != shift:
                 raise ValueError("the potential table must share the field table's lattice")
             self.atab = torch.from_numpy(np.ascontiguousarray(atab)).to("cuda")
-            aE, bE, cE = self.coeffs[:3]
-            # a at tau = -1/2 (the phase of the zero momentum) at each start
-            m = aE * -0.5 + bE * ((wl.x0 - wl.x_origin) / wl.dx - 0.5) + cE
-            mf = np.floor(m)
-            j0 = mf.astype(np.int64) % aM
-            j1 = (j0 + 1) % aM
-            self.ai = atab[j0] + (m - mf) * (atab[j1] - atab[j0])
+            self.ai = initial_potential(wl, atab, aM, self.coeffs)
         self.pusher = picsub.Pusher(num=wl.num, ncells=wl.ncells, order=wl.order, dx=wl.dx,
                                     dt=wl.dt, psi_max=wl.psi_max, x_origin=wl.x_origin,
                                     k_max=k_max, ring_depth=self.S + wl.order,
@@ -189,7 +204,6 @@ class PulseRun:
         self.shift = 0
         self.n = 0
         self.windows = []            # (n, steps, shift) of every launch
-        self.xi_end = W.GAUSS_XI0 + 7.0 * W.GAUSS_SIGMA
 
     def reset(self):
         if self.shift:
@@ -206,11 +220,9 @@ class PulseRun:
         """One launch; False once the pulse has passed every live electron."""
         wl = self.wl
         d = self.pusher.diag()
+        if pulse_passed(wl, self.n, d["x"], d["status"]):
+            return False
         live = d["status"] == 0
-        if not live.any():
-            return False
-        if np.all(self.n * wl.dt - d["x"][live] > self.xi_end):
-            return False
         target = int(np.floor((d["x"][live].min() - wl.x_origin) / wl.dx)) - self.left
         if target != self.shift:
             self.pusher.grid_shift(target - self.shift)
@@ -243,3 +255,127 @@ class PulseRun:
 
     def close(self):
         self.pusher.close()
+
+
+class PulseBatch:
+    """Several runs of the model problem (one pulse workload per run, all of
+    one interpolation order) in one batch context, pushed together in
+    launches of S steps.  Before each launch every run's grid is moved so
+    that its leftmost live electron sits `left` cells from node 0 (the rule of
+    PulseRun) and the run's levels are sampled for the moved nodes.  A run is
+    finished at the first launch boundary where the pulse has passed its
+    electrons, or where it has taken step_cap[r] steps (an electron that the
+    integrator's errors keep riding with the pulse): its results are read
+    then ("pulse_passed" tells which), and it is pushed on with the others
+    (nothing it recorded changes).  The batch ends when every run is
+    finished.  With energy=True the energy error of Eq. (gamma error) is
+    kept as well."""
+
+    def __init__(self, wls, *, S: int = 1000, precision: str = "fp64", k_max: int = 12,
+                 left: int = 8, energy: bool = True, step_cap=None, stream=None):
+        import torch
+        self.wls = list(wls)
+        order = self.wls[0].order
+        for wl in self.wls:
+            if wl.kind != "gauss" or wl.order != order:
+                raise ValueError("a pulse batch holds Gaussian-pulse workloads of one order")
+            if wl.ncells < left + int(S * wl.dt / wl.dx) + 16:
+                raise ValueError("a grid is too short for S steps")
+        self.S, self.left, self.order, self.energy = int(S), int(left), order, bool(energy)
+        self.src = []           # (table, M, coeffs, potential table) per run
+        ai = []
+        runs = []
+        for wl in self.wls:
+            table, M, shift = wl.table()
+            co = W.shifted_coeffs(wl.lat, shift)
+            atab = None
+            if self.energy:
+                at, aM, ashift = wl.potential()
+                if aM != M or ashift != shift:
+                    raise ValueError("the potential table must share the field table's lattice")
+                atab = torch.from_numpy(np.ascontiguousarray(at)).to("cuda")
+                ai.append(initial_potential(wl, at, M, co))
+            self.src.append((torch.from_numpy(np.ascontiguousarray(table)).to("cuda"), int(M),
+                             co, atab))
+            runs.append((wl.num, picsub.make_params(
+                ncells=wl.ncells, order=order, dx=wl.dx, dt=wl.dt, psi_max=wl.psi_max,
+                x_origin=wl.x_origin, k_max=k_max, ring_depth=self.S + order,
+                precision=precision, binning="none")))
+        self.pusher = picsub.Pusher(runs=runs, stream=stream)
+        self.first = np.cumsum([0] + [wl.num for wl in self.wls])
+        self.ai = np.concatenate(ai) if self.energy else None
+        self.shift = [0] * len(self.wls)
+        self.step_cap = [None] * len(self.wls) if step_cap is None else list(step_cap)
+
+    def reset(self):
+        for r, sh in enumerate(self.shift):
+            if sh:
+                self.pusher.grid_shift(-sh, run=r)
+        self.shift = [0] * len(self.wls)
+        self.pusher.particles_set(np.concatenate([wl.x0 for wl in self.wls]),
+                                  *[np.concatenate([wl.p0[c] for wl in self.wls])
+                                    for c in range(3)])
+        self.pusher.diag_track(True)
+        if self.energy:
+            self.pusher.gamma_error_start(self.ai)
+        self.n = 0
+        self.windows = [[] for _ in self.wls]     # (n, steps, shift) of each run's launches
+        self.results = [None] * len(self.wls)
+
+    def _record(self, r, d, passed):
+        sl = slice(int(self.first[r]), int(self.first[r + 1]))
+        _, rmax = self.pusher.dephasing_read()
+        out = {"steps_run": self.n, "pulse_passed": passed, "windows": list(self.windows[r]),
+               "counters": self.pusher.run_counters(r),
+               "x": d["x"][sl], "px": d["px"][sl], "py": d["py"][sl], "pz": d["pz"][sl],
+               "status": d["status"][sl], "eps_dephasing": rmax[sl],
+               "gamma_max": self.pusher.gamma_max_read()[sl]}
+        if self.energy:
+            out["eps_energy"] = self.pusher.gamma_error_read()[sl]
+        return out
+
+    def window(self) -> bool:
+        """One launch of every run; False once every run is finished."""
+        d = self.pusher.diag()
+        for r, wl in enumerate(self.wls):
+            sl = slice(int(self.first[r]), int(self.first[r + 1]))
+            if self.results[r] is not None:
+                continue
+            passed = pulse_passed(wl, self.n, d["x"][sl], d["status"][sl])
+            cap = self.step_cap[r]
+            if passed or (cap is not None and self.n >= cap):
+                self.results[r] = self._record(r, d, passed)
+        if all(res is not None for res in self.results):
+            return False
+        p = self.order
+        for r, wl in enumerate(self.wls):
+            sl = slice(int(self.first[r]), int(self.first[r + 1]))
+            live = d["status"][sl] == 0
+            if live.any():
+                target = int(np.floor((d["x"][sl][live].min() - wl.x_origin) / wl.dx)) - self.left
+                if target != self.shift[r]:
+                    self.pusher.grid_shift(target - self.shift[r], run=r)
+                    self.shift[r] = target
+            table, M, co, atab = self.src[r]
+            sh = self.shift[r]
+            cos = (co[0], co[1], co[2] + co[1] * sh, co[3], co[4], co[5] + co[4] * sh)
+            self.pusher.fields_load_lattice_r(r, self.n - p, p + self.S, table, M, cos)
+            if self.energy:
+                self.pusher.gamma_error_lattice(atab, M, cos[:3], run=r)
+            if self.results[r] is None:
+                self.windows[r].append((self.n, self.S, sh))
+        self.pusher.push(self.n, self.S)
+        self.n += self.S
+        return True
+
+    def unfinished(self) -> int:
+        return sum(res is None for res in self.results)
+
+    def run(self, max_steps: int = 1 << 40):
+        while self.n < max_steps and self.window():
+            pass
+        return self.results
+
+    def close(self):
+        self.pusher.close()
+
