@@ -177,6 +177,26 @@ __device__ constexpr double mono_c(int field, int m, int j)
     }
 }
 
+// a_m = sum_j C[m][j] F_j, j ascending, leaving out the zero entries of C
+// (E's a_0 is the newest level itself): the entries are compile-time
+// constants once the loops are unrolled, so the tests fold away.  Dropping a
+// zero term changes no value (only, at most, the sign of an exact zero).
+template <int P, int FIELD>
+__device__ __forceinline__ double mono_row(const double (&F)[P + 1], int m)
+{
+    double v = 0.0;
+    bool first = true;
+#pragma unroll
+    for (int j = 0; j <= P; ++j) {
+        const double c = mono_c<P>(FIELD, m, j);
+        if (c != 0.0) {
+            v = first ? c * F[j] : fma(c, F[j], v);
+            first = false;
+        }
+    }
+    return v;
+}
+
 // Replace the level rows of the LDS window (row 2j: E of level j, 2j + 1: B,
 // nodes 0 .. nn - 1) by the monomial coefficients (row 2m: a_m of E, 2m + 1:
 // of B), one node per lane, both fields (the field is then known at compile
@@ -189,12 +209,7 @@ __device__ __forceinline__ void column_to_monomial(double *col)
 #pragma unroll
     for (int j = 0; j <= P; ++j) F[j] = col[2 * j * WWIN];
 #pragma unroll
-    for (int m = 0; m <= P; ++m) {
-        double v = mono_c<P>(FIELD, m, 0) * F[0];
-#pragma unroll
-        for (int j = 1; j <= P; ++j) v = fma(mono_c<P>(FIELD, m, j), F[j], v);
-        col[2 * m * WWIN] = v;
-    }
+    for (int m = 0; m <= P; ++m) col[2 * m * WWIN] = mono_row<P, FIELD>(F, m);
 }
 
 template <int P>
@@ -220,10 +235,7 @@ __device__ __forceinline__ double horner_ring(gdptr ring, const int32_t (&off)[P
     // each coefficient is formed just before Horner's rule takes it (the
     // same operations; fewer values live at once)
     auto coeff = [&](int m) {
-        double c = mono_c<P>(field, m, 0) * F[0];
-#pragma unroll
-        for (int j = 1; j <= P; ++j) c = fma(mono_c<P>(field, m, j), F[j], c);
-        return c;
+        return field ? mono_row<P, 1>(F, m) : mono_row<P, 0>(F, m);
     };
     double v = coeff(P);
 #pragma unroll
@@ -454,10 +466,11 @@ __global__ void __launch_bounds__(64 * WPG)
         }
         const bool heavy = live && k > 0;
 
-        // E of level n at x_n for a k = 0 step (s = 1/2 is the time of level n:
-        // E's weights are (0, .., 0, 1)), read before the window is converted
+        // E of level n at x_n (s = 1/2 is the time of level n: E's weights are
+        // (0, .., 0, 1)), for a k = 0 step and for the first sub-step of a
+        // sub-cycled one; read before the window is converted
         double Ek = 0.0;
-        if (live & (k == 0)) {
+        if (live) {
             const double uE = x - 0.5;
             const double flE = floor(uE);
             const int iE = int(flE);
@@ -534,7 +547,18 @@ __global__ void __launch_bounds__(64 * WPG)
                 const double *Wk = MONO ? nullptr : a.wtab + wtab_offset(k) * STRIDE;
                 done = true;
                 for (int j = 1; j <= nsub; ++j, u += fnew) {
-                    if (j > 1 && !(x >= 0.5 && x < ncm1)) {
+                    // sub-step 1 is at x_n and s = 1/2: its fields are the
+                    // decision's B and level n's E (the same operations on the
+                    // same values as the interpolant's evaluation at u = 0)
+                    if (j == 1) {
+                        const double vb = deph ? py * ig : 0.0;
+                        boris_fma(c1, Ek, Bd, onepz, px, py);
+                        ig = rsq_1nr(fma(px, px, fma(py, py, onepz)));
+                        x = fma(rdx, px * ig, x);
+                        if (deph) swork += sub_step_work(c1, Ek, vb, py * ig);
+                        continue;
+                    }
+                    if (!(x >= 0.5 && x < ncm1)) {
                         done = false;
                         break;
                     }
@@ -576,10 +600,10 @@ __global__ void __launch_bounds__(64 * WPG)
                     }
                     const double Es = tent_fma(uE - fe, e0, e1);
                     const double vb = deph ? py * ig : 0.0;
-                    boris_fma(j == 1 ? c1 : cn, Es, tent_fma(x - fb, bb0, bb1), onepz, px, py);
+                    boris_fma(cn, Es, tent_fma(x - fb, bb0, bb1), onepz, px, py);
                     ig = rsq_1nr(fma(px, px, fma(py, py, onepz)));
                     x = fma(rdx, px * ig, x);
-                    if (deph) swork += sub_step_work(j == 1 ? c1 : cn, Es, vb, py * ig);
+                    if (deph) swork += sub_step_work(cn, Es, vb, py * ig);
                 }
                 if (!done) status = PIC_PARTICLE_LOST;
             }
