@@ -43,6 +43,8 @@ KERNELS = {  # (kernel name in traces, sources it is built from)
     "fp64": ("push_wave_kernel<3, 1, false, false>", ("push_wave.hpp", "common.hpp")),
     "fp64fast": ("push_fast_kernel<3, 1, false, false, 0>", ("push_fast.hpp", "common.hpp")),
     "fp64fast/occ5": ("push_fast_kernel<3, 1, false, false, 5>", ("push_fast.hpp", "common.hpp")),
+    "fp64fast/occ6": ("push_fast_kernel<3, 1, false, false, 6>", ("push_fast.hpp", "common.hpp")),
+    "fp64fast/occ7": ("push_fast_kernel<3, 1, false, false, 7>", ("push_fast.hpp", "common.hpp")),
     "fp32c": ("push_wave_fp32c_kernel<3, 1, false>", ("push_f32c.hpp", "push_fast.hpp",
                                                         "common.hpp")),
     "ballot": ("push_tile_kernel<3, 256, false>", ("push_tile.hpp", "common.hpp")),
@@ -404,7 +406,7 @@ def main():
     ap.add_argument("--periods", type=float, default=100.0)
     ap.add_argument("--order", type=int, default=3, choices=(1, 2, 3, 5),
                     help="single runs: temporal interpolation order p")
-    ap.add_argument("--occupancy", default="auto", choices=("auto", "0", "5"),
+    ap.add_argument("--occupancy", default="auto", choices=("auto", "0", "5", "6", "7"),
                     help="register budget of the FP64_FAST push at orders 1, 3 (pic_tune): "
                          "auto times one untimed pass with each and keeps the faster")
     ap.add_argument("--pb-width", type=float, default=0.0625,
@@ -461,7 +463,7 @@ def main():
     if args.precision == "fp64fast" and order <= 3 and args.binning != "ballot":
         if args.occupancy == "auto":
             occ_trials = {}
-            for occ in (0, 5):
+            for occ in (0, 5, 6, 7):
                 main_pass.pusher.tune_set(occupancy=occ)
                 main_pass.step()                          # warm-up with this budget
                 torch.cuda.synchronize()
@@ -485,8 +487,8 @@ def main():
     model_step = model_flops(counters, order)
     achieved = flops_step * args.steps / (kernel_ms / 1e3) / 1e12
     key = "ballot" if args.binning == "ballot" else args.precision
-    if key == "fp64fast" and occupancy == 5:
-        key = "fp64fast/occ5"
+    if key == "fp64fast" and occupancy:
+        key = f"fp64fast/occ{occupancy}"
     traffic = (measured_traffic(key, launches_per_step, args.workload)
                if args.fields == "lattice" and order == 3 and not args.num and args.periods == 100.0
                else None)

@@ -442,12 +442,14 @@ typedef struct {
                                 PIC_BIN_BALLOT (compaction kernel, FP64) */
     int32_t sort_sub;        /* position bins per cell of the load-time
                                 sort, 1..256 (next pic_particles_set) */
-    int32_t occupancy;       /* PIC_FP64_FAST at orders 1 and 3 with one
+    int32_t occupancy;       /* PIC_FP64_FAST at orders 1 to 3 with one
                                 wavefront per workgroup: 0 = the compiler's
-                                register budget (4 wavefronts per SIMD),
-                                5 = a budget for 5 (a few registers spill;
+                                register budget, 5, 6 or 7 = a budget for
+                                that many wavefronts per SIMD (at 6 and 7 a
+                                few registers spill, reloaded on sub-cycled
+                                steps); the same bits under every budget;
                                 which is faster depends on the workload,
-                                pic_autotune times both) */
+                                pic_autotune times them all */
 } pic_tune;
 
 pic_status pic_tune_set(pic_ctx *ctx, const pic_tune *t);

@@ -379,9 +379,18 @@ void launch_wave(const PushArgs &a, int precision, int occupancy, hipStream_t s)
     if (precision == PIC_FP64) {
         if (a.ktrace) push_wave_kernel<P, WPG, DIAG, true><<<grid, block, 0, s>>>(a);
         else push_wave_kernel<P, WPG, DIAG, false><<<grid, block, 0, s>>>(a);
-    } else if (precision == PIC_FP64_FAST && occupancy == 5 && WPG == 1 && !DIAG && P <= 3) {
-        if (a.ktrace) push_fast_kernel<P, 1, false, true, 5><<<grid, block, 0, s>>>(a);
-        else push_fast_kernel<P, 1, false, false, 5><<<grid, block, 0, s>>>(a);
+    } else if (precision == PIC_FP64_FAST && occupancy >= 5 && WPG == 1 && !DIAG && P <= 3) {
+        // register budgets for 5, 6 or 7 wavefronts per SIMD
+        if (occupancy == 5) {
+            if (a.ktrace) push_fast_kernel<P, 1, false, true, 5><<<grid, block, 0, s>>>(a);
+            else push_fast_kernel<P, 1, false, false, 5><<<grid, block, 0, s>>>(a);
+        } else if (occupancy == 6) {
+            if (a.ktrace) push_fast_kernel<P, 1, false, true, 6><<<grid, block, 0, s>>>(a);
+            else push_fast_kernel<P, 1, false, false, 6><<<grid, block, 0, s>>>(a);
+        } else {
+            if (a.ktrace) push_fast_kernel<P, 1, false, true, 7><<<grid, block, 0, s>>>(a);
+            else push_fast_kernel<P, 1, false, false, 7><<<grid, block, 0, s>>>(a);
+        }
     } else if (precision == PIC_FP64_FAST) {
         if (a.ktrace) push_fast_kernel<P, WPG, DIAG, true><<<grid, block, 0, s>>>(a);
         else push_fast_kernel<P, WPG, DIAG, false><<<grid, block, 0, s>>>(a);
@@ -1435,7 +1444,8 @@ pic_status pic_tune_set(pic_ctx *ctx, const pic_tune *t)
     if (t->binning == PIC_BIN_BALLOT && ctx->precision != PIC_FP64)
         return fail(ctx, PIC_E_ARG, "the tiled ballot push runs with PIC_FP64 only");
     if (t->sort_sub < 1 || t->sort_sub > 256) return fail(ctx, PIC_E_ARG, "sort_sub must be in [1, 256]");
-    if (t->occupancy != 0 && t->occupancy != 5) return fail(ctx, PIC_E_ARG, "occupancy must be 0 or 5");
+    if (t->occupancy != 0 && (t->occupancy < 5 || t->occupancy > 7))
+        return fail(ctx, PIC_E_ARG, "occupancy must be 0, 5, 6 or 7");
     ctx->tune = *t;
     return PIC_OK;
 }
@@ -1543,7 +1553,7 @@ pic_status pic_autotune(pic_ctx *ctx, int32_t steps, int32_t reps, pic_tune *bes
     const pic_tune &cur = ctx->tune;
     for (int w : {1, 2, 4}) cand.push_back(pic_tune{w, cur.tile, PIC_BIN_NONE, cur.sort_sub, 0});
     if (ctx->precision == PIC_FP64_FAST && ctx->order <= 3)
-        cand.push_back(pic_tune{1, cur.tile, PIC_BIN_NONE, cur.sort_sub, 5});
+        for (int occ : {5, 6, 7}) cand.push_back(pic_tune{1, cur.tile, PIC_BIN_NONE, cur.sort_sub, occ});
     if (ctx->precision == PIC_FP64)
         for (int t : {128, 256, 512})
             cand.push_back(pic_tune{cur.waves_per_group, t, PIC_BIN_BALLOT, cur.sort_sub, 0});

@@ -380,14 +380,14 @@ def test_fp32c_large_case(torch_gpu, runner, seed):
 
 @pytest.mark.parametrize("order", [1, 3])
 def test_fp64fast_register_budget_changes_nothing(torch_gpu, runner, order):
-    """occupancy = 5 compiles the same arithmetic for 5 wavefronts per SIMD
-    (a few registers spill): the bits, counters and k trace are those of the
-    default budget."""
+    """occupancy = 5, 6, 7 compile the same arithmetic for that many
+    wavefronts per SIMD (registers spill at 6 and 7): the bits, counters and
+    k trace are those of the default budget."""
     torch = torch_gpu
     wl = W.make_workload("th", 3000, 100.0, 75, 500, 4, order, 0.01, 4.0, seed=41,
                          theta=10.0 / 511.0)
     out = []
-    for occ in (0, 5):
+    for occ in (0, 5, 6, 7):
         run = runner.DeviceRun(wl, S=wl.steps, binning="none", precision="fp64fast")
         run.pusher.tune_set(occupancy=occ)
         run.reset()
@@ -397,13 +397,20 @@ def test_fp64fast_register_budget_changes_nothing(torch_gpu, runner, order):
         d = run.diag()
         out.append((d, buf.cpu().numpy()))
         run.close()
-    (d0, k0), (d5, k5) = out
-    for key in ("x", "px", "py", "pz", "k_last", "status"):
-        assert np.array_equal(d0[key], d5[key]), key
-    assert d0["counters"] == d5["counters"] and np.array_equal(k0, k5)
+    run = runner.DeviceRun(wl, S=wl.steps, binning="none", precision="fp64fast")
+    for bad in (4, 8):
+        with pytest.raises(Exception):
+            run.pusher.tune_set(occupancy=bad)
+    run.close()
+    d0, k0 = out[0]
+    for d5, k5 in out[1:]:
+        for key in ("x", "px", "py", "pz", "k_last", "status"):
+            assert np.array_equal(d0[key], d5[key]), key
+        assert d0["counters"] == d5["counters"] and np.array_equal(k0, k5)
 
 
-@pytest.mark.parametrize("precision,occ", [("fp64fast", 0), ("fp64fast", 5), ("fp64", 0)])
+@pytest.mark.parametrize("precision,occ", [("fp64fast", 0), ("fp64fast", 5), ("fp64fast", 7),
+                                           ("fp64", 0)])
 def test_trace_buffer_changes_nothing(torch_gpu, runner, precision, occ):
     """A launch with a k-trace buffer attached runs a kernel with the trace
     compiled in, one without runs a kernel without it: the same bits and
