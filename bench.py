@@ -345,6 +345,27 @@ class Pass:
         self.run.close()
 
 
+OCC_BUDGETS = (0, 5, 6, 7)      # register budgets of the fast push (pic_tune.occupancy)
+
+
+def trial_occupancy(p):
+    """Time one untimed pass of p at each register budget (after one at that
+    budget to warm up) and leave p at the fastest; (budget, {budget: ms})."""
+    import torch
+    trials = {}
+    for occ in OCC_BUDGETS:
+        p.pusher.tune_set(occupancy=occ)
+        p.step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p.step()
+        torch.cuda.synchronize()
+        trials[occ] = (time.perf_counter() - t0) * 1e3
+    best = min(trials, key=trials.get)
+    p.pusher.tune_set(occupancy=best)
+    return best, trials
+
+
 def make_workload(name: str, args):
     """(workload, description) of one of the four workload shapes."""
     from paper_2102_10983_amd import workloads as W
@@ -462,16 +483,7 @@ def main():
     occupancy = 0
     if args.precision == "fp64fast" and order <= 3 and args.binning != "ballot":
         if args.occupancy == "auto":
-            occ_trials = {}
-            for occ in (0, 5, 6, 7):
-                main_pass.pusher.tune_set(occupancy=occ)
-                main_pass.step()                          # warm-up with this budget
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                main_pass.step()
-                torch.cuda.synchronize()
-                occ_trials[occ] = (time.perf_counter() - t0) * 1e3
-            occupancy = min(occ_trials, key=occ_trials.get)
+            occupancy, occ_trials = trial_occupancy(main_pass)
         else:
             occupancy = int(args.occupancy)
         main_pass.pusher.tune_set(occupancy=occupancy)
@@ -577,6 +589,11 @@ def main():
                      occupancy if prec == "fp64fast" else 0, graph=leg_graph,
                      reorder=leg_reorder)
             p.pb_width = args.pb_width
+            leg_occ = occupancy if prec == "fp64fast" else 0
+            lorder = lwl[0].order if isinstance(lwl, list) else lwl.order
+            if (prec == "fp64fast" and lorder <= 3 and binning != "ballot" and not leg_graph
+                    and args.occupancy == "auto"):
+                leg_occ, _ = trial_occupancy(p)      # each leg at its own fastest budget
             ev = []
             t = p.time(nsteps, 1, stream, ev)
             c = p.pusher.counters()
@@ -588,7 +605,8 @@ def main():
                    "steps": nsteps, "ms_per_step": t / nsteps * 1e3,
                    "value": c["sub_steps"] * nsteps / t,
                    "push_ms": sum(a.elapsed_time(b) for a, b in ev) / nsteps,
-                   "sub_steps_per_pass": c["sub_steps"]}
+                   "sub_steps_per_pass": c["sub_steps"],
+                   **({"occupancy": leg_occ} if prec == "fp64fast" else {})}
             if wname == args.workload:
                 leg["same_sub_steps"] = c["sub_steps"] == sub_per_step
             if fields == "yee":
