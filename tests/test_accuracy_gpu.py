@@ -125,15 +125,16 @@ def test_batch_full_scale_sampled(torch_gpu):
 
 
 def test_benchmark_configuration_sampled(torch_gpu):
-    """Exactly what bench.py times on its default workload: 2^20 electrons,
-    a0 = 150, learned group order, the 5-wavefront register budget, 7500
-    steps in one launch; 2048 consecutive electrons against the oracle."""
+    """The large case as its bench leg runs it: 2^20 electrons, a0 = 150,
+    learned group order, the six-wavefront register budget its trial picks,
+    7500 steps in one launch; 2048 consecutive electrons against the
+    oracle."""
     torch = torch_gpu
     from paper_2102_10983_amd import predictor, runner
     from parity import compare
     wl = W.large_case(seed=22)
     run = runner.DeviceRun(wl, S=wl.steps, precision="fp64fast", binning="none")
-    run.pusher.tune_set(occupancy=5)
+    run.pusher.tune_set(occupancy=6)
     run.reset()
     predictor.Predictor.load().prebin(run.pusher, wl.a0, n=0)
     first = int(np.random.default_rng(23).integers(0, wl.num - 2048))
@@ -151,14 +152,16 @@ def test_benchmark_configuration_sampled(torch_gpu):
 
 
 def test_predictor_workload_sampled(torch_gpu):
-    """The learned-binning workload: 2^22 electrons at rest over 16
-    wavelengths, a0 = 150, 16384 cells, 100 periods in one launch, learned
-    order; 2048 consecutive electrons against the oracle."""
+    """Exactly what bench.py times by default, the learned-binning workload:
+    2^22 electrons at rest over 16 wavelengths, a0 = 150, 16384 cells, 100
+    periods in one launch, learned order, the seven-wavefront register
+    budget its trial picks; 2048 consecutive electrons against the oracle."""
     torch = torch_gpu
     from paper_2102_10983_amd import predictor, runner
     from parity import compare
     wl = W.predictor_case()
     run = runner.DeviceRun(wl, S=wl.steps, precision="fp64fast", binning="none")
+    run.pusher.tune_set(occupancy=7)
     run.reset()
     predictor.Predictor.load().prebin(run.pusher, wl.a0, n=0)
     first = int(np.random.default_rng(29).integers(0, wl.num - 2048))
