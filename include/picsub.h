@@ -456,8 +456,8 @@ pic_status pic_tune_set(pic_ctx *ctx, const pic_tune *t);
 pic_status pic_tune_get(const pic_ctx *ctx, pic_tune *t);
 
 /* Time `reps` device-driven windows of `steps` steps for each candidate
- * launch shape (1, 2, 4 wavefronts per workgroup; the 5-wavefront register
- * budget with PIC_FP64_FAST at orders 1 and 3; compaction tiles of 128,
+ * launch shape (1, 2, 4 wavefronts per workgroup; the 5-, 6- and 7-wavefront
+ * register budgets with PIC_FP64_FAST at orders 1 to 3; compaction tiles of 128,
  * 256, 512 with PIC_FP64), restoring the state after every trial, and keep
  * the fastest.  Requires sources on all runs.  The winner is remembered
  * for the process under the configuration's signature (device, precision,
